@@ -1,0 +1,190 @@
+/*
+ * msa_oracle.c -- plain, slow, single-threaded reference for optimal
+ * k-sequence alignment by dynamic programming.  TEST INFRASTRUCTURE ONLY:
+ * called by the test suite, the smoke check and the benchmark's CPU-baseline
+ * leg, never by the GPU library.  Shares no code with the GPU path.
+ *
+ * Every step follows the definition in the paper (Helal et al.):
+ *   cell tensor   : shape (n_i + 1), the "+1" being the initial gap character
+ *                   (Section 3.2, the (8,8,8,8) -> (9,9,9,9), 6561-cell example)
+ *   recurrence    : Eq. 1 (Section 2) for two sequences, generalised to the
+ *                   2^k - 1 lower neighbours of a cell (Section 2)
+ *   column score  : sum of pairs, gap-gap = 0 (Section 5.2)
+ *   initial cell  : initialised, here to 0 (Section 4, scoring of a cell)
+ *   traceback     : walk from the end of the tensor back to the origin
+ *                   following the optimal choices (Section 2)
+ * No blocking, fusion or reordering: cells are visited in row-major order
+ * (every lower neighbour v - b precedes v in that order), each candidate is
+ * scored by building its column and summing its pairs.
+ */
+#include "msa_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+#define GAP_SYM (-1)
+
+/* Score of one pair of column entries (Section 5.2 scheme, Eq. 1 terms). */
+static int64_t pair_score(int x, int y, int32_t alpha, const int32_t *sub,
+                          int32_t gap) {
+  if (x == GAP_SYM && y == GAP_SYM) return 0;          /* gap-gap pair */
+  if (x == GAP_SYM || y == GAP_SYM) return gap;        /* residue-gap pair */
+  return sub[(int64_t)x * alpha + y];                  /* sub(a_i, b_j) */
+}
+
+/* Column produced when stepping into cell v from v - b: sequence i
+ * contributes residue s_i[v_i - 1] when bit i of b is set, a gap otherwise. */
+static void build_column(int32_t k, const int64_t *v, int b,
+                         const uint8_t *const *seqs, int *col) {
+  for (int i = 0; i < k; ++i)
+    col[i] = ((b >> i) & 1) ? (int)seqs[i][v[i] - 1] : GAP_SYM;
+}
+
+/* Sum-of-pairs score of a column. */
+static int64_t sp_score(int32_t k, const int *col, int32_t alpha,
+                        const int32_t *sub, int32_t gap) {
+  int64_t s = 0;
+  for (int i = 0; i < k; ++i)
+    for (int j = i + 1; j < k; ++j) s += pair_score(col[i], col[j], alpha, sub, gap);
+  return s;
+}
+
+static int validate(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                    int32_t alpha, const int32_t *sub) {
+  if (k < 2 || k > MSA_ORACLE_MAX_K || !lens || !seqs || !sub) return -1;
+  if (alpha < 1 || alpha > 255) return -1;
+  for (int i = 0; i < k; ++i) {
+    if (lens[i] < 0) return -1;
+    if (lens[i] > 0 && !seqs[i]) return -1;
+    for (int32_t t = 0; t < lens[i]; ++t)
+      if (seqs[i][t] >= alpha) return -1;
+  }
+  return 0;
+}
+
+/* Full fill: score tensor xi (int64) and decision tensor D (lowest
+ * maximising mask).  Row-major strides, last sequence fastest. */
+static int fill(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                int32_t alpha, const int32_t *sub, int32_t gap, int64_t *xi,
+                uint8_t *D) {
+  int64_t stride[MSA_ORACLE_MAX_K];
+  int64_t ncell = 1;
+  for (int i = k - 1; i >= 0; --i) {
+    stride[i] = ncell;
+    ncell *= (int64_t)lens[i] + 1;
+  }
+  int64_t v[MSA_ORACLE_MAX_K];
+  int col[MSA_ORACLE_MAX_K];
+  const int nmask = 1 << k;
+  for (int64_t lin = 0; lin < ncell; ++lin) {
+    /* coordinates of cell lin */
+    int64_t rem = lin;
+    for (int i = 0; i < k; ++i) {
+      v[i] = rem / stride[i];
+      rem -= v[i] * stride[i];
+    }
+    if (lin == 0) { /* initial cell */
+      xi[0] = 0;
+      D[0] = 0;
+      continue;
+    }
+    int have = 0;
+    int64_t best = 0;
+    int bestb = 0;
+    for (int b = 1; b < nmask; ++b) {
+      /* neighbour v - b must lie inside the tensor */
+      int ok = 1;
+      int64_t pred = lin;
+      for (int i = 0; i < k; ++i) {
+        if ((b >> i) & 1) {
+          if (v[i] == 0) { ok = 0; break; }
+          pred -= stride[i];
+        }
+      }
+      if (!ok) continue;
+      build_column(k, v, b, seqs, col);
+      int64_t cand = xi[pred] + sp_score(k, col, alpha, sub, gap);
+      /* strictly greater: among equal candidates the first (lowest b) stays */
+      if (!have || cand > best) {
+        best = cand;
+        bestb = b;
+        have = 1;
+      }
+    }
+    xi[lin] = best;
+    D[lin] = (uint8_t)bestb;
+  }
+  return 0;
+}
+
+int msa_oracle_fill(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                    int32_t alpha, const int32_t *sub, int32_t gap,
+                    int64_t *score_tensor_out, uint8_t *dir_out) {
+  if (validate(k, lens, seqs, alpha, sub) != 0 || !score_tensor_out) return -1;
+  int64_t ncell = 1;
+  for (int i = 0; i < k; ++i) ncell *= (int64_t)lens[i] + 1;
+  uint8_t *D = dir_out ? dir_out : (uint8_t *)malloc((size_t)ncell);
+  if (!D) return -1;
+  fill(k, lens, seqs, alpha, sub, gap, score_tensor_out, D);
+  if (!dir_out) free(D);
+  return 0;
+}
+
+int msa_oracle_align(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                     int32_t alpha, const int32_t *sub, int32_t gap,
+                     int64_t *score_out, uint8_t *dir_out, uint8_t *aln_out,
+                     int64_t aln_cap, int64_t *aln_len_out) {
+  if (validate(k, lens, seqs, alpha, sub) != 0) return -1;
+  if (!score_out || !aln_out || !aln_len_out) return -1;
+  int64_t total = 0;
+  for (int i = 0; i < k; ++i) total += lens[i];
+  if (aln_cap < total) return -1;
+
+  int64_t stride[MSA_ORACLE_MAX_K];
+  int64_t ncell = 1;
+  for (int i = k - 1; i >= 0; --i) {
+    stride[i] = ncell;
+    ncell *= (int64_t)lens[i] + 1;
+  }
+  int64_t *xi = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+  uint8_t *D = dir_out ? dir_out : (uint8_t *)malloc((size_t)ncell);
+  /* columns are emitted end-first during the walk, then reversed */
+  uint8_t *rev = (uint8_t *)malloc((size_t)(total > 0 ? total : 1) * (size_t)k);
+  if (!xi || !D || !rev) {
+    free(xi);
+    if (!dir_out) free(D);
+    free(rev);
+    return -1;
+  }
+  fill(k, lens, seqs, alpha, sub, gap, xi, D);
+
+  /* traceback from the far corner to the origin */
+  int64_t v[MSA_ORACLE_MAX_K];
+  int64_t lin = 0;
+  for (int i = 0; i < k; ++i) {
+    v[i] = lens[i];
+    lin += v[i] * stride[i];
+  }
+  int64_t L = 0;
+  while (lin != 0) {
+    int b = D[lin];
+    for (int i = 0; i < k; ++i) {
+      if ((b >> i) & 1) {
+        rev[L * k + i] = seqs[i][v[i] - 1];
+        v[i] -= 1;
+        lin -= stride[i];
+      } else {
+        rev[L * k + i] = MSA_ORACLE_GAP;
+      }
+    }
+    ++L;
+  }
+  for (int64_t c = 0; c < L; ++c)
+    for (int i = 0; i < k; ++i) aln_out[i * aln_cap + c] = rev[(L - 1 - c) * k + i];
+  *score_out = xi[ncell - 1];
+  *aln_len_out = L;
+  free(xi);
+  if (!dir_out) free(D);
+  free(rev);
+  return 0;
+}

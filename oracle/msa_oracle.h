@@ -1,0 +1,73 @@
+/*
+ * msa_oracle.h -- reference (oracle) implementation of optimal k-sequence
+ * alignment by full dynamic programming.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may call this.  It shares no code, header,
+ * table or helper with the GPU library; neither side includes the other.
+ *
+ * What it computes (Helal et al., "Parallelizing Optimal Multiple Sequence
+ * Alignment by Dynamic Programming"):
+ *   - Section 2, Eq. 1: the pairwise recurrence max over three neighbours of
+ *     (neighbour score + substitution score or gap score);
+ *   - Section 2 (text after Eq. 1): its generalisation to k sequences, where a
+ *     cell of the k-dimensional tensor of shape (n_i + 1) takes the maximum over
+ *     its 2^k - 1 lower neighbours;
+ *   - Section 5.2: the sum-of-pairs column score (residue-residue pairs use the
+ *     substitution score, residue-gap pairs score the gap value, gap-gap pairs
+ *     score 0);
+ *   - Section 2 (traceback): the optimal alignment is recovered by walking
+ *     back from the end of the tensor to the origin along optimal choices.
+ *
+ * Readings taken where the paper is silent (all listed in the design notes):
+ *   - global alignment: the walk starts at the far corner (n_0, ..., n_{k-1});
+ *   - the origin scores 0, and a neighbour outside the tensor is not a
+ *     candidate;
+ *   - ties go to the lowest neighbour bitmask b, where bit i of b set means
+ *     "sequence i contributes its residue to this column";
+ *   - the gap value is added per residue-gap pair (a penalty is negative).
+ *
+ * Exact integer arithmetic (int64); no rounding anywhere.
+ */
+#ifndef MSA_ORACLE_H
+#define MSA_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSA_ORACLE_GAP 0xFF /* gap symbol in the returned alignment rows */
+#define MSA_ORACLE_MAX_K 8
+
+/*
+ * Align k sequences (2 <= k <= 8).
+ *   seqs[i]    : lens[i] residue codes in [0, alpha)
+ *   sub        : alpha x alpha substitution scores, row-major, symmetric
+ *   gap        : score added for each residue-gap pair in a column
+ *   score_out  : optimal sum-of-pairs score
+ *   dir_out    : optional (may be NULL); prod(lens[i] + 1) bytes, row-major
+ *                with the last sequence's index fastest; dir_out[v] is the
+ *                chosen neighbour mask b at cell v (0 at the origin)
+ *   aln_out    : k rows of aln_cap bytes; row i is sequence i with gaps
+ *                written as MSA_ORACLE_GAP, columns from origin to end
+ *   aln_len_out: number of columns L
+ * Returns 0, or -1 on invalid input / allocation failure (outputs untouched).
+ */
+int msa_oracle_align(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                     int32_t alpha, const int32_t *sub, int32_t gap,
+                     int64_t *score_out, uint8_t *dir_out,
+                     uint8_t *aln_out, int64_t aln_cap, int64_t *aln_len_out);
+
+/*
+ * Score every cell: writes the full int64 score tensor (prod(lens[i]+1)
+ * entries, same layout as dir_out) without a traceback.  Returns 0 or -1.
+ */
+int msa_oracle_fill(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                    int32_t alpha, const int32_t *sub, int32_t gap,
+                    int64_t *score_tensor_out, uint8_t *dir_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
