@@ -1,0 +1,213 @@
+/*
+ * msa_dp.h -- C ABI of an MI355X (gfx950) library for optimal multiple
+ * sequence alignment by full k-dimensional dynamic programming.
+ *
+ * Method (Helal et al., "Parallelizing Optimal Multiple Sequence Alignment by
+ * Dynamic Programming"):
+ *   - Section 2, Eq. 1 and the paragraph after it: k sequences of lengths n_i
+ *     span a k-dimensional tensor of shape (n_i + 1); every cell takes the
+ *     maximum over its 2^k - 1 lower neighbours v - b (b a nonempty subset of
+ *     the sequences) of  score(v - b) + column score(v, b).
+ *   - Section 5.2: the column score is the sum over sequence pairs of
+ *     sub(x, y) for two residues, `gap` for a residue and a gap, 0 for two gaps.
+ *   - Section 4 (scoring of a cell): the initial cell is initialised (to 0).
+ *   - Section 2 (traceback): the alignment is read back from the end of the
+ *     tensor to the origin following the optimal choices.
+ *   - Section 3 (partitions of edge S grouped in computation waves of equal
+ *     distance from the origin; Eqs. 2-3, Tables 1-2): the GPU fill cuts the
+ *     tensor into hypercube tiles and schedules them by the same wave order.
+ * Readings where the paper is silent: global alignment (walk starts at the
+ * far corner); out-of-range neighbours are not candidates; ties go to the
+ * lowest neighbour mask b (bit i = sequence i contributes a residue).
+ *
+ * Conventions for every entry point:
+ *   - Residues are codes in [0, alpha), alpha <= 255; `submat` is alpha x alpha
+ *     int8, row-major, and must be symmetric.
+ *   - `gap` is ADDED per residue-gap pair (penalties are negative).
+ *   - 2 <= k <= MSA_MAX_K; lengths >= 0 (empty sequences allowed).
+ *   - An alignment is k rows of `aln_cap` bytes (row i at offset i*aln_cap);
+ *     row i is sequence i with gaps written as MSA_GAP_CODE; columns run from
+ *     the origin to the end; aln_cap must be >= sum of the lengths.
+ *   - All arithmetic is exact integer arithmetic (int32 on the device after
+ *     a closed-form range check, MSA_ERANGE if it cannot be guaranteed).
+ *   - Return value: MSA_OK (0) or a negative status.  On error no output is
+ *     written (for the asynchronous device entry points: see each call).
+ *   - The library keeps no caller pointer after a call returns, except where
+ *     stated (server jobs).
+ */
+#ifndef MSA_DP_H
+#define MSA_DP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSA_MAX_K 8          /* a direction byte holds the 2^k - 1 masks */
+#define MSA_GAP_CODE 0xFF    /* gap symbol in alignment rows */
+
+enum {
+  MSA_OK = 0,
+  MSA_EINVAL = -1,     /* bad argument (k, lengths, codes, matrix, capacity) */
+  MSA_ERANGE = -2,     /* score range does not fit the device integer width */
+  MSA_ENOMEM = -3,     /* workspace larger than the device or the budget */
+  MSA_EDEVICE = -4,    /* HIP error or device watchdog timeout */
+  MSA_EAGAIN = -5,     /* server: result not ready yet */
+  MSA_ESHUTDOWN = -6   /* server: handle is shutting down */
+};
+
+/* Human-readable text for a status code (static storage). */
+const char *msa_strerror(int status);
+
+/* ------------------------------------------------------------------------
+ * Plain path, host buffers.
+ * Aligns k sequences: seqs[i] points to lens[i] host bytes.  Device memory
+ * is managed internally (a per-thread cache keyed by the shape, reused by
+ * later calls of the same shape).  Synchronous.
+ *   score_out   : optimal sum-of-pairs score
+ *   aln_out     : k rows of aln_cap bytes (host)
+ *   aln_len_out : number of alignment columns L
+ * Errors: MSA_EINVAL, MSA_ERANGE, MSA_ENOMEM, MSA_EDEVICE.
+ * ---------------------------------------------------------------------- */
+int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
+                 const int8_t *submat, int32_t alpha, int32_t gap,
+                 int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
+                 int64_t *aln_len_out);
+
+/* ------------------------------------------------------------------------
+ * Plain path, device-resident buffers (the form the benchmark times).
+ *
+ * msa_dp_workspace_bytes: device workspace needed for one alignment of the
+ *   given lengths (tile edge chosen by the library for k).  Returns the byte
+ *   count (> 0) or a negative status (MSA_EINVAL / MSA_ENOMEM on overflow).
+ *
+ * msa_dp_prepare: one-time set-up of a caller-allocated workspace for the
+ *   given shape and scoring: validates, checks the score range, writes the
+ *   tile schedule and the substitution matrix into the workspace (host to
+ *   device copies on `hip_stream`).  Must be called before the first
+ *   msa_dp_align_dev on that workspace and again whenever lens, k, submat,
+ *   alpha or gap change.  d_workspace must be 256-byte aligned and hold
+ *   msa_dp_workspace_bytes(lens, k) bytes.
+ *
+ * msa_dp_align_dev: enqueue one alignment on `hip_stream` (a hipStream_t,
+ *   NULL = default stream).  Asynchronous: returns after launching.
+ *   d_seqs      : device bytes, the k sequences concatenated (sum lens)
+ *   d_score     : device int64, optimal score
+ *   d_aln       : device, k rows of aln_cap bytes
+ *   d_aln_len   : device int64, L
+ *   d_status    : device int32, MSA_OK or MSA_EINVAL (a residue code
+ *                 >= alpha) or MSA_EDEVICE (watchdog); outputs are
+ *                 meaningful only when it reads MSA_OK
+ *   Host-detectable errors (bad k/lens/cap, unprepared or mismatched
+ *   workspace, launch failure) are returned immediately and nothing is
+ *   enqueued.  Calls on one workspace must be stream-ordered.
+ * ---------------------------------------------------------------------- */
+int64_t msa_dp_workspace_bytes(const int32_t *lens, int32_t k);
+
+int msa_dp_prepare(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
+                   int32_t k, const int8_t *submat, int32_t alpha,
+                   int32_t gap, void *hip_stream);
+
+int msa_dp_align_dev(void *d_workspace, int64_t ws_bytes,
+                     const uint8_t *d_seqs, const int32_t *lens, int32_t k,
+                     int64_t *d_score, uint8_t *d_aln, int64_t aln_cap,
+                     int64_t *d_aln_len, int32_t *d_status, void *hip_stream);
+
+/* Copy the decision tensor of the last alignment run on `d_workspace` into
+ * d_dir_out: prod(lens[i] + 1) bytes, row-major with the last sequence's
+ * index fastest, byte = chosen neighbour mask b (0 at the origin).  For
+ * verification.  Asynchronous on hip_stream. */
+int msa_dp_export_dirs(void *d_workspace, int64_t ws_bytes,
+                       const int32_t *lens, int32_t k, uint8_t *d_dir_out,
+                       void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Batched path: many independent alignments (uneven k and lengths) through
+ * one persistent kernel per group of jobs whose workspaces fit
+ * `hbm_budget_bytes` (0 = a default fraction of free device memory).
+ * Synchronous.  Job inputs are host pointers read during the call.
+ * results[i].aln must point to k * results[i].aln_cap host bytes; the call
+ * writes status, score and aln_len of every result.  Returns MSA_OK when
+ * the batch ran (per-job errors are in results[i].status), or a negative
+ * status for a whole-call failure.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t k;
+  const uint8_t *seqs[MSA_MAX_K];  /* host, lens[i] bytes each */
+  int32_t lens[MSA_MAX_K];
+  const int8_t *submat;            /* host, alpha x alpha */
+  int32_t alpha;
+  int32_t gap;
+} msa_job;
+
+typedef struct {
+  int32_t status;    /* MSA_OK or a negative status for this job */
+  int64_t score;
+  uint8_t *aln;      /* caller-owned, k rows of aln_cap bytes */
+  int64_t aln_cap;
+  int64_t aln_len;
+} msa_result;
+
+int msa_dp_align_batch(const msa_job *jobs, int32_t njobs,
+                       msa_result *results, int64_t hbm_budget_bytes);
+
+/* ------------------------------------------------------------------------
+ * Served path: a request loop that admits jobs as device memory (the HBM
+ * budget) and launch slots free up, keeps their state on the device and runs
+ * several persistent launches concurrently (continuous batching).
+ *
+ * msa_server_create: hbm_budget_bytes (0 = default), max_inflight = maximum
+ *   concurrent launches (streams), max_jobs_per_launch.  NULL on failure.
+ * msa_server_submit: copies the job's inputs; *ticket identifies it.
+ *   MSA_EINVAL / MSA_ERANGE for invalid jobs, MSA_ENOMEM when the job alone
+ *   exceeds the whole budget, MSA_ESHUTDOWN after destroy started.
+ * msa_server_poll: MSA_EAGAIN while running; otherwise fills *out (out->aln
+ *   and out->aln_cap supplied by the caller), returns the job status and
+ *   forgets the ticket.  MSA_EINVAL for an unknown ticket.
+ * msa_server_wait: like poll but blocks up to timeout_us (< 0 = forever);
+ *   MSA_EAGAIN on timeout.
+ * msa_server_destroy: waits for in-flight launches, frees everything.
+ * Thread-safe: submit/poll/wait may be called from several threads.
+ * ---------------------------------------------------------------------- */
+typedef struct msa_server msa_server;
+
+msa_server *msa_server_create(int64_t hbm_budget_bytes, int32_t max_inflight,
+                              int32_t max_jobs_per_launch);
+int msa_server_submit(msa_server *srv, const msa_job *job, uint64_t *ticket);
+int msa_server_poll(msa_server *srv, uint64_t ticket, msa_result *out);
+int msa_server_wait(msa_server *srv, uint64_t ticket, msa_result *out,
+                    int64_t timeout_us);
+void msa_server_destroy(msa_server *srv);
+
+/* ------------------------------------------------------------------------
+ * Host-side helpers (no device needed), exposed for tests and tools.
+ * ---------------------------------------------------------------------- */
+
+/* Closed-form bounds on every cell score (any alignment of prefixes):
+ * for gap <= 0, lo = gap*(k-1)*sum(n_i) (all single-residue columns) and
+ * hi = max(0, max sub) * sum_{i<j} min(n_i, n_j); otherwise
+ * +-sum(n_i)*C(k,2)*max(|gap|, max|sub|).  Returns MSA_OK or MSA_EINVAL. */
+int msa_dp_score_bounds(const int32_t *lens, int32_t k, const int8_t *submat,
+                        int32_t alpha, int32_t gap, int64_t *lo, int64_t *hi);
+
+/* Tile edge (interior cells per dimension) the library uses for k. */
+int32_t msa_dp_tile_edge(int32_t k);
+
+/* Tile grid of a shape: tiles_per_dim[i] = 1 + ceil(n_i / T) (the extra tile
+ * is the one-cell-thick initial-gap layer v_i = 0); returns the number of
+ * tile waves (sum of tiles_per_dim - k + 1), or a negative status. */
+int32_t msa_dp_tile_grid(const int32_t *lens, int32_t k, int32_t tile_edge,
+                         int32_t *tiles_per_dim);
+
+/* Number of tiles in each computation wave (tiles whose coordinates sum to
+ * w) of a grid with p[i] tiles along dimension i (Section 3.1-3.2, Eqs. 2-3,
+ * Tables 1-2).  Writes counts[0 .. waves-1] and returns the wave count
+ * sum(p) - k + 1, or a negative status (cap too small / bad input). */
+int32_t msa_dp_wave_counts(const int32_t *p, int32_t k, int64_t *counts,
+                           int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSA_DP_H */

@@ -1,0 +1,341 @@
+"""ctypes binding of ``libmsa_dp.so`` (argument marshalling only).
+
+Every step of the alignment runs in the library's HIP kernels; this module
+only converts Python/numpy/torch arguments into pointers and sizes.  PyTorch
+supplies device memory and streams.  If the shared library is missing the
+import of any entry point raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+PKG = Path(__file__).resolve().parent
+LIB_PATH = PKG / "_lib" / "libmsa_dp.so"
+
+MAX_K = 8
+GAP = 0xFF
+
+MSA_OK, MSA_EINVAL, MSA_ERANGE, MSA_ENOMEM, MSA_EDEVICE, MSA_EAGAIN, MSA_ESHUTDOWN = (
+    0, -1, -2, -3, -4, -5, -6)
+
+_lib = None
+
+c_i32p = ctypes.POINTER(ctypes.c_int32)
+c_i64p = ctypes.POINTER(ctypes.c_int64)
+c_vp = ctypes.c_void_p
+
+
+class MsaError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = lib().msa_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+
+
+class MsaJob(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32),
+                ("seqs", c_vp * MAX_K),
+                ("lens", ctypes.c_int32 * MAX_K),
+                ("submat", c_vp),
+                ("alpha", ctypes.c_int32),
+                ("gap", ctypes.c_int32)]
+
+
+class MsaResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32),
+                ("score", ctypes.c_int64),
+                ("aln", c_vp),
+                ("aln_cap", ctypes.c_int64),
+                ("aln_len", ctypes.c_int64)]
+
+
+_SIGS = {
+    "msa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "msa_dp_align": (ctypes.c_int, [ctypes.POINTER(c_vp), c_i32p, ctypes.c_int32, c_vp,
+                                    ctypes.c_int32, ctypes.c_int32, c_i64p, c_vp,
+                                    ctypes.c_int64, c_i64p]),
+    "msa_dp_workspace_bytes": (ctypes.c_int64, [c_i32p, ctypes.c_int32]),
+    "msa_dp_prepare": (ctypes.c_int, [c_vp, ctypes.c_int64, c_i32p, ctypes.c_int32, c_vp,
+                                      ctypes.c_int32, ctypes.c_int32, c_vp]),
+    "msa_dp_align_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p, ctypes.c_int32,
+                                        c_vp, c_vp, ctypes.c_int64, c_vp, c_vp, c_vp]),
+    "msa_dp_export_dirs": (ctypes.c_int, [c_vp, ctypes.c_int64, c_i32p, ctypes.c_int32,
+                                          c_vp, c_vp]),
+    "msa_dp_align_batch": (ctypes.c_int, [ctypes.POINTER(MsaJob), ctypes.c_int32,
+                                          ctypes.POINTER(MsaResult), ctypes.c_int64]),
+    "msa_server_create": (c_vp, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
+    "msa_server_submit": (ctypes.c_int, [c_vp, ctypes.POINTER(MsaJob),
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+    "msa_server_poll": (ctypes.c_int, [c_vp, ctypes.c_uint64, ctypes.POINTER(MsaResult)]),
+    "msa_server_wait": (ctypes.c_int, [c_vp, ctypes.c_uint64, ctypes.POINTER(MsaResult),
+                                       ctypes.c_int64]),
+    "msa_server_destroy": (None, [c_vp]),
+    "msa_dp_score_bounds": (ctypes.c_int, [c_i32p, ctypes.c_int32, c_vp, ctypes.c_int32,
+                                           ctypes.c_int32, c_i64p, c_i64p]),
+    "msa_dp_tile_edge": (ctypes.c_int32, [ctypes.c_int32]),
+    "msa_dp_tile_grid": (ctypes.c_int32, [c_i32p, ctypes.c_int32, ctypes.c_int32, c_i32p]),
+    "msa_dp_wave_counts": (ctypes.c_int32, [c_i32p, ctypes.c_int32, c_i64p, ctypes.c_int32]),
+}
+
+
+def lib():
+    """Load the library (raises FileNotFoundError when it was not built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise FileNotFoundError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2311_17530_amd.build`")
+        h = ctypes.CDLL(str(LIB_PATH))
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def _i32arr(xs):
+    return (ctypes.c_int32 * len(xs))(*[int(x) for x in xs])
+
+
+def _check(rc, what):
+    if rc != MSA_OK:
+        raise MsaError(rc, what)
+
+
+# ---------------------------------------------------------------------------
+# host helpers
+# ---------------------------------------------------------------------------
+def strerror(status: int) -> str:
+    return lib().msa_strerror(int(status)).decode()
+
+
+def score_bounds(lens, sub, gap):
+    sub = np.ascontiguousarray(np.asarray(sub, dtype=np.int8))
+    lo, hi = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib().msa_dp_score_bounds(_i32arr(lens), len(lens), sub.ctypes.data, sub.shape[0],
+                                   int(gap), ctypes.byref(lo), ctypes.byref(hi))
+    _check(rc, "msa_dp_score_bounds")
+    return lo.value, hi.value
+
+
+def tile_edge(k: int) -> int:
+    return int(lib().msa_dp_tile_edge(int(k)))
+
+
+def tile_grid(lens, tile):
+    out = (ctypes.c_int32 * len(lens))()
+    w = lib().msa_dp_tile_grid(_i32arr(lens), len(lens), int(tile), out)
+    if w < 0:
+        raise MsaError(w, "msa_dp_tile_grid")
+    return list(out), int(w)
+
+
+def wave_counts(p):
+    cap = sum(p) + 1
+    out = (ctypes.c_int64 * cap)()
+    w = lib().msa_dp_wave_counts(_i32arr(p), len(p), out, cap)
+    if w < 0:
+        raise MsaError(w, "msa_dp_wave_counts")
+    return [int(x) for x in out[:w]]
+
+
+def workspace_bytes(lens) -> int:
+    n = int(lib().msa_dp_workspace_bytes(_i32arr(lens), len(lens)))
+    if n < 0:
+        raise MsaError(n, "msa_dp_workspace_bytes")
+    return n
+
+
+# ---------------------------------------------------------------------------
+# plain path, host buffers
+# ---------------------------------------------------------------------------
+def align(seqs, sub, gap):
+    """Optimal alignment through ``msa_dp_align`` (host buffers).
+
+    Returns ``(score, rows)`` with rows a (k, L) uint8 array (GAP for gaps)."""
+    seqs = [np.ascontiguousarray(np.asarray(s, dtype=np.uint8)) for s in seqs]
+    sub = np.ascontiguousarray(np.asarray(sub, dtype=np.int8))
+    k = len(seqs)
+    cap = max(1, sum(len(s) for s in seqs))
+    out = np.full((k, cap), GAP, dtype=np.uint8)
+    ptrs = (c_vp * k)(*[s.ctypes.data if len(s) else None for s in seqs])
+    score, alen = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib().msa_dp_align(ptrs, _i32arr([len(s) for s in seqs]), k, sub.ctypes.data,
+                            sub.shape[0], int(gap), ctypes.byref(score), out.ctypes.data,
+                            cap, ctypes.byref(alen))
+    _check(rc, "msa_dp_align")
+    return int(score.value), out[:, : alen.value].copy()
+
+
+# ---------------------------------------------------------------------------
+# plain path, device buffers (torch provides memory and the stream)
+# ---------------------------------------------------------------------------
+class DeviceAligner:
+    """Device-resident alignment of one fixed shape and scoring.
+
+    Owns a torch-allocated workspace and output tensors on ``device``; ``run``
+    enqueues one alignment on the current torch stream (asynchronous)."""
+
+    def __init__(self, lens, sub, gap, device="cuda"):
+        import torch
+        self.torch = torch
+        self.lens = [int(x) for x in lens]
+        self.k = len(self.lens)
+        self.device = torch.device(device)
+        self.sub = np.ascontiguousarray(np.asarray(sub, dtype=np.int8))
+        self.gap = int(gap)
+        self.ws_bytes = workspace_bytes(self.lens)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) & ~255
+        self.cap = max(1, sum(self.lens))
+        self.d_seqs = torch.zeros(max(1, sum(self.lens)), dtype=torch.uint8, device=self.device)
+        self.d_aln = torch.full((self.k, self.cap), GAP, dtype=torch.uint8, device=self.device)
+        self.d_score = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.d_len = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.d_status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        rc = lib().msa_dp_prepare(self.ws_ptr, self.ws_bytes, _i32arr(self.lens), self.k,
+                                  self.sub.ctypes.data, self.sub.shape[0], self.gap,
+                                  self._stream())
+        _check(rc, "msa_dp_prepare")
+
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def set_sequences(self, seqs):
+        flat = np.concatenate([np.asarray(s, dtype=np.uint8) for s in seqs]) if sum(
+            self.lens) else np.zeros(1, np.uint8)
+        if [len(s) for s in seqs] != self.lens:
+            raise ValueError("sequence lengths differ from the prepared shape")
+        self.d_seqs[: len(flat)].copy_(self.torch.from_numpy(flat))
+
+    def run(self):
+        rc = lib().msa_dp_align_dev(self.ws_ptr, self.ws_bytes, self.d_seqs.data_ptr(),
+                                    _i32arr(self.lens), self.k, self.d_score.data_ptr(),
+                                    self.d_aln.data_ptr(), self.cap, self.d_len.data_ptr(),
+                                    self.d_status.data_ptr(), self._stream())
+        _check(rc, "msa_dp_align_dev")
+
+    def result(self):
+        """Synchronise and return ``(score, rows)`` (raises on device status)."""
+        self.torch.cuda.current_stream(self.device).synchronize()
+        st = int(self.d_status.item())
+        if st != MSA_OK:
+            raise MsaError(st, "device status")
+        L = int(self.d_len.item())
+        rows = self.d_aln[:, :L].cpu().numpy()
+        return int(self.d_score.item()), rows
+
+    def export_dirs(self):
+        """Row-major decision tensor (neighbour mask per cell) of the last run."""
+        shape = tuple(n + 1 for n in self.lens)
+        out = self.torch.empty(int(np.prod(shape)), dtype=self.torch.uint8, device=self.device)
+        rc = lib().msa_dp_export_dirs(self.ws_ptr, self.ws_bytes, _i32arr(self.lens), self.k,
+                                      out.data_ptr(), self._stream())
+        _check(rc, "msa_dp_export_dirs")
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return out.cpu().numpy().reshape(shape)
+
+
+# ---------------------------------------------------------------------------
+# batched and served paths
+# ---------------------------------------------------------------------------
+def _make_job(seqs, sub, gap, keep):
+    seqs = [np.ascontiguousarray(np.asarray(s, dtype=np.uint8)) for s in seqs]
+    sub = np.ascontiguousarray(np.asarray(sub, dtype=np.int8))
+    keep.append((seqs, sub))
+    j = MsaJob()
+    j.k = len(seqs)
+    for i, s in enumerate(seqs):
+        j.seqs[i] = s.ctypes.data if len(s) else None
+        j.lens[i] = len(s)
+    j.submat = sub.ctypes.data
+    j.alpha = sub.shape[0]
+    j.gap = int(gap)
+    return j
+
+
+def align_batch(jobs, hbm_budget_bytes: int = 0):
+    """Align many jobs (each ``(seqs, sub, gap)``) in persistent launches.
+
+    Returns a list of ``(status, score, rows)``."""
+    keep = []
+    n = len(jobs)
+    cj = (MsaJob * n)()
+    cr = (MsaResult * n)()
+    outs = []
+    for i, (seqs, sub, gap) in enumerate(jobs):
+        cj[i] = _make_job(seqs, sub, gap, keep)
+        cap = max(1, sum(len(s) for s in seqs))
+        buf = np.full((len(seqs), cap), GAP, dtype=np.uint8)
+        outs.append(buf)
+        cr[i].aln = buf.ctypes.data
+        cr[i].aln_cap = cap
+    rc = lib().msa_dp_align_batch(cj, n, cr, int(hbm_budget_bytes))
+    _check(rc, "msa_dp_align_batch")
+    res = []
+    for i in range(n):
+        r = cr[i]
+        res.append((int(r.status), int(r.score), outs[i][:, : r.aln_len].copy()))
+    return res
+
+
+class Server:
+    """Continuous-batching alignment server (``msa_server_*``)."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_inflight: int = 4,
+                 max_jobs_per_launch: int = 256):
+        self.h = lib().msa_server_create(int(hbm_budget_bytes), int(max_inflight),
+                                         int(max_jobs_per_launch))
+        if not self.h:
+            raise MsaError(MSA_EDEVICE, "msa_server_create")
+        self._caps = {}
+
+    def submit(self, seqs, sub, gap) -> int:
+        keep = []
+        j = _make_job(seqs, sub, gap, keep)
+        t = ctypes.c_uint64()
+        rc = lib().msa_server_submit(self.h, ctypes.byref(j), ctypes.byref(t))
+        _check(rc, "msa_server_submit")
+        self._caps[t.value] = (len(seqs), max(1, sum(len(s) for s in seqs)))
+        return int(t.value)
+
+    def _result(self, ticket, timeout_us=None):
+        k, cap = self._caps[ticket]
+        buf = np.full((k, cap), GAP, dtype=np.uint8)
+        r = MsaResult()
+        r.aln = buf.ctypes.data
+        r.aln_cap = cap
+        if timeout_us is None:
+            rc = lib().msa_server_poll(self.h, ticket, ctypes.byref(r))
+        else:
+            rc = lib().msa_server_wait(self.h, ticket, ctypes.byref(r), int(timeout_us))
+        if rc == MSA_EAGAIN:
+            return None
+        del self._caps[ticket]
+        return int(r.status), int(r.score), buf[:, : r.aln_len].copy()
+
+    def poll(self, ticket):
+        return self._result(ticket)
+
+    def wait(self, ticket, timeout_us=-1):
+        return self._result(ticket, timeout_us)
+
+    def close(self):
+        if self.h:
+            lib().msa_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,252 @@
+// msa_abi.cpp -- C ABI of the library: plain (host and device buffer) paths,
+// host-side helpers.  The batched and served paths live in msa_batch.cpp.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "../../include/msa_dp.h"
+#include "msa_plan.h"
+#include "msa_runtime.h"
+
+using namespace msa;
+
+extern "C" const char *msa_strerror(int status) {
+  switch (status) {
+    case MSA_OK: return "ok";
+    case MSA_EINVAL: return "invalid argument";
+    case MSA_ERANGE: return "score range exceeds the device integer width";
+    case MSA_ENOMEM: return "workspace exceeds the device memory or the budget";
+    case MSA_EDEVICE: return "device error or watchdog timeout";
+    case MSA_EAGAIN: return "result not ready";
+    case MSA_ESHUTDOWN: return "server is shutting down";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int msa_dp_score_bounds(const int32_t *lens, int32_t k, const int8_t *submat,
+                                   int32_t alpha, int32_t gap, int64_t *lo, int64_t *hi) {
+  return score_bounds(lens, k, submat, alpha, gap, lo, hi);
+}
+
+extern "C" int32_t msa_dp_tile_edge(int32_t k) {
+  if (k < 2 || k > MSA_MAX_K) return MSA_EINVAL;
+  return tile_edge_for_k(k);
+}
+
+extern "C" int32_t msa_dp_tile_grid(const int32_t *lens, int32_t k, int32_t tile_edge,
+                                    int32_t *tiles_per_dim) {
+  if (!lens || !tiles_per_dim || k < 2 || k > MSA_MAX_K || tile_edge < 1) return MSA_EINVAL;
+  int32_t waves = 1 - k;
+  for (int i = 0; i < k; ++i) {
+    if (lens[i] < 0) return MSA_EINVAL;
+    tiles_per_dim[i] = 1 + (lens[i] + tile_edge - 1) / tile_edge;
+    waves += tiles_per_dim[i];
+  }
+  return waves;
+}
+
+extern "C" int32_t msa_dp_wave_counts(const int32_t *p, int32_t k, int64_t *counts,
+                                      int32_t cap) {
+  if (!p || !counts || k < 1 || k > MSA_MAX_K) return MSA_EINVAL;
+  int32_t waves = 1 - k;
+  for (int i = 0; i < k; ++i) {
+    if (p[i] < 1) return MSA_EINVAL;
+    waves += p[i];
+  }
+  if (cap < waves) return MSA_EINVAL;
+  // polynomial product  prod_i (1 + x + ... + x^{p_i - 1}): coefficient w
+  // counts the tiles whose coordinates sum to w
+  std::vector<int64_t> poly(1, 1);
+  for (int i = 0; i < k; ++i) {
+    std::vector<int64_t> nxt(poly.size() + p[i] - 1, 0);
+    for (size_t a = 0; a < poly.size(); ++a)
+      for (int b = 0; b < p[i]; ++b) nxt[a + b] += poly[a];
+    poly.swap(nxt);
+  }
+  for (int32_t w = 0; w < waves; ++w) counts[w] = poly[w];
+  return waves;
+}
+
+static int validate_shape(const int32_t *lens, int32_t k) {
+  if (!lens || k < 2 || k > MSA_MAX_K) return MSA_EINVAL;
+  for (int i = 0; i < k; ++i)
+    if (lens[i] < 0) return MSA_EINVAL;
+  return MSA_OK;
+}
+
+extern "C" int64_t msa_dp_workspace_bytes(const int32_t *lens, int32_t k) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  return p.bytes;
+}
+
+extern "C" int msa_dp_prepare(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
+                              int32_t k, const int8_t *submat, int32_t alpha, int32_t gap,
+                              void *hip_stream) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255)) return MSA_EINVAL;
+  rc = check_scoring(lens, k, submat, alpha, gap);
+  if (rc) return rc;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  if (ws_bytes < p.bytes) return MSA_EINVAL;
+  return prepare_workspace(p, (char *)d_workspace, submat, alpha, gap, (hipStream_t)hip_stream);
+}
+
+extern "C" int msa_dp_align_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
+                                const int32_t *lens, int32_t k, int64_t *d_score,
+                                uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len,
+                                int32_t *d_status, void *hip_stream) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255) || !d_score || !d_aln_len || !d_status)
+    return MSA_EINVAL;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  if (ws_bytes < p.bytes || aln_cap < p.total_len || (p.total_len > 0 && !d_aln) ||
+      (p.total_len > 0 && !d_seqs))
+    return MSA_EINVAL;
+  return run_plain(p, (char *)d_workspace, d_seqs, d_score, d_aln, aln_cap, d_aln_len,
+                   d_status, (hipStream_t)hip_stream);
+}
+
+extern "C" int msa_dp_export_dirs(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
+                                  int32_t k, uint8_t *d_dir_out, void *hip_stream) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!d_workspace || !d_dir_out) return MSA_EINVAL;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  if (ws_bytes < p.bytes) return MSA_EINVAL;
+  return export_dirs(p, (char *)d_workspace, d_dir_out, (hipStream_t)hip_stream);
+}
+
+// ---------------------------------------------------------------------------
+// Host-buffer convenience path: a per-thread cache of device buffers.
+// ---------------------------------------------------------------------------
+namespace {
+struct HostCache {
+  int device = -1;
+  void *ws = nullptr;
+  int64_t ws_bytes = 0;
+  uint8_t *io = nullptr;  // seqs | aln | score | len | status
+  int64_t io_bytes = 0;
+  // signature of the prepared workspace
+  int32_t k = 0, lens[MSA_MAX_K] = {}, alpha = 0, gap = 0;
+  std::vector<int8_t> sub;
+  hipStream_t stream = nullptr;
+  ~HostCache() {
+    // process exit: the runtime may already be torn down; leak rather than fault
+  }
+};
+thread_local HostCache g_cache;
+}  // namespace
+
+extern "C" int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
+                            const int8_t *submat, int32_t alpha, int32_t gap,
+                            int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
+                            int64_t *aln_len_out) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!seqs || !score_out || !aln_len_out) return MSA_EINVAL;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  if (aln_cap < p.total_len || (p.total_len > 0 && !aln_out)) return MSA_EINVAL;
+  for (int i = 0; i < k; ++i)
+    if (lens[i] > 0 && !seqs[i]) return MSA_EINVAL;
+  for (int i = 0; i < k; ++i)
+    for (int32_t t = 0; t < lens[i]; ++t)
+      if (seqs[i][t] >= alpha) return MSA_EINVAL;
+  rc = check_scoring(lens, k, submat, alpha, gap);
+  if (rc) return rc;
+
+  HostCache &c = g_cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MSA_EDEVICE;
+  if (c.device != dev) {
+    c = HostCache();
+    c.device = dev;
+    if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess)
+      return MSA_EDEVICE;
+  }
+  const int64_t io_need = ((p.total_len + 255) & ~255LL) + k * ((aln_cap + 255) & ~255LL) + 256;
+  if (c.ws_bytes < p.bytes) {
+    if (c.ws) (void)hipFree(c.ws);
+    c.ws = nullptr;
+    c.ws_bytes = 0;
+    c.k = 0;
+    if (hipMalloc(&c.ws, p.bytes) != hipSuccess) {
+      c.ws = nullptr;
+      return MSA_ENOMEM;
+    }
+    c.ws_bytes = p.bytes;
+  }
+  if (c.io_bytes < io_need) {
+    if (c.io) (void)hipFree(c.io);
+    c.io = nullptr;
+    c.io_bytes = 0;
+    if (hipMalloc(&c.io, io_need) != hipSuccess) {
+      c.io = nullptr;
+      return MSA_ENOMEM;
+    }
+    c.io_bytes = io_need;
+  }
+  bool same = c.k == k && c.alpha == alpha && c.gap == gap &&
+              (int64_t)c.sub.size() == (int64_t)alpha * alpha &&
+              memcmp(c.sub.data(), submat, (size_t)alpha * alpha) == 0;
+  for (int i = 0; same && i < k; ++i) same = c.lens[i] == lens[i];
+  if (!same) {
+    rc = prepare_workspace(p, (char *)c.ws, submat, alpha, gap, c.stream);
+    if (rc) {
+      c.k = 0;
+      return rc;
+    }
+    c.k = k;
+    c.alpha = alpha;
+    c.gap = gap;
+    for (int i = 0; i < k; ++i) c.lens[i] = lens[i];
+    c.sub.assign(submat, submat + (size_t)alpha * alpha);
+  }
+  uint8_t *d_seqs = c.io;
+  uint8_t *d_aln = d_seqs + ((p.total_len + 255) & ~255LL);
+  int64_t *d_misc = (int64_t *)(d_aln + k * ((aln_cap + 255) & ~255LL));
+  int64_t off = 0;
+  for (int i = 0; i < k; ++i) {
+    if (lens[i] > 0 &&
+        hipMemcpyAsync(d_seqs + off, seqs[i], lens[i], hipMemcpyHostToDevice, c.stream) !=
+            hipSuccess)
+      return MSA_EDEVICE;
+    off += lens[i];
+  }
+  rc = run_plain(p, (char *)c.ws, d_seqs, d_misc, d_aln, aln_cap, d_misc + 1,
+                 (int32_t *)(d_misc + 2), c.stream);
+  if (rc) return rc;
+  int64_t misc[3] = {0, 0, 0};
+  if (hipMemcpyAsync(misc, d_misc, sizeof(misc), hipMemcpyDeviceToHost, c.stream) !=
+      hipSuccess)
+    return MSA_EDEVICE;
+  if (hipStreamSynchronize(c.stream) != hipSuccess) return MSA_EDEVICE;
+  const int32_t st = (int32_t)(misc[2] & 0xffffffff);
+  if (st != MSA_OK) return st;
+  const int64_t L = misc[1];
+  if (L > 0) {
+    if (hipMemcpy2DAsync(aln_out, aln_cap, d_aln, aln_cap, L, k, hipMemcpyDeviceToHost,
+                         c.stream) != hipSuccess)
+      return MSA_EDEVICE;
+    if (hipStreamSynchronize(c.stream) != hipSuccess) return MSA_EDEVICE;
+  }
+  *score_out = misc[0];
+  *aln_len_out = L;
+  return MSA_OK;
+}

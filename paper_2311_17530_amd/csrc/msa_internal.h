@@ -1,0 +1,81 @@
+// msa_internal.h -- structures shared by the host core and the HIP kernels of
+// the library (not part of the public ABI).
+//
+// Tiling (Section 3 of the paper: hypercube partitions of edge S that overlap
+// their lower neighbours by one layer, scheduled in computation waves of
+// equal distance from the origin).  Here a tile has edge T = S - 1 interior
+// cells plus a one-cell halo.  Along dimension i the tile coordinate c runs
+// over [0, P_i) with P_i = 1 + ceil(n_i / T):
+//   c = 0      : the one-cell-thick initial-gap layer v_i = 0;
+//   c >= 1     : cells v_i in [(c-1)T + 1, min(cT, n_i)].
+// The halo of a tile along i is the layer v_i = lo_i - 1, i.e. the last layer
+// of tile c - 1 (or, for c = 0, a virtual layer of -infinity).  Every cell
+// belongs to exactly one tile, so the fill needs no special boundary code:
+// an out-of-range neighbour reads -infinity and never wins.
+#pragma once
+#include <stdint.h>
+
+namespace msa {
+
+constexpr int kMaxK = 8;
+constexpr int kNegKey = -(1 << 30);  // "-infinity" key; see range check
+
+// Device-visible description of one alignment job.  Lives in the workspace
+// (plain path) or in the batch descriptor array (batched / served paths).
+struct JobDev {
+  int32_t k, T, alpha, gap;
+  int32_t n[kMaxK];            // sequence lengths
+  int32_t P[kMaxK];            // tiles per dimension (incl. the v_i = 0 layer)
+  int32_t tstride[kMaxK];      // row-major tile strides (last dim fastest)
+  int32_t ntiles;
+  int32_t nwaves;              // sum(P) - k + 1
+  int32_t dbs;                 // direction block stride (T^k rounded to 16)
+  int32_t seq_off[kMaxK];      // offsets of each sequence in the seq buffer
+  int64_t face_off[kMaxK];     // element offset of face array i in `faces`
+  int64_t fplane[kMaxK];       // elements per face plane of dimension i
+  int64_t fstride[kMaxK][kMaxK];  // face-plane strides: fstride[i][j], j != i
+  int64_t total_len;           // sum of lengths (traceback path capacity)
+  // device pointers (filled per call for the plain path)
+  const uint8_t *seqs;         // concatenated sequences
+  const int8_t *sub;           // alpha x alpha
+  const uint32_t *cells;       // per-(k,T) hyperplane-sorted cell table
+  const int32_t *hstart;       // hyperplane starts into `cells`, H + 1 entries
+  int32_t *faces;              // face planes (int32 keys)
+  uint8_t *dir;                // tile-major direction blocks
+  int32_t *flags;              // per-tile completion epoch
+  uint8_t *path;               // traceback masks, end first
+  int64_t *score_out;
+  uint8_t *aln_out;
+  int64_t aln_cap;
+  int64_t *aln_len_out;
+  int32_t *status_out;
+};
+
+// Control block of one persistent launch (in device memory).
+struct Ctrl {
+  int32_t head;     // next queue slot
+  int32_t epoch;    // flags equal to epoch mean "tile done in this launch"
+  int32_t status;   // MSA_OK, MSA_EINVAL (bad code), MSA_EDEVICE (watchdog)
+  int32_t alpha;    // scoring fixed at set-up (plain path)
+  int32_t gap;
+  int32_t pad[59];
+};
+
+// One entry of the batched tile queue: (job index, tile linear index).
+struct QItem {
+  int32_t job;
+  int32_t tile;
+};
+
+// Tile edge per k (LDS footprint (T+1)^k * 4 bytes for the score tile).
+constexpr int tile_edge_for_k(int k) {
+  return k == 2 ? 32 : k == 3 ? 16 : k == 4 ? 8 : k == 5 ? 5 : k == 6 ? 3 : 2;
+}
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+constexpr int bits_for(int x) {  // bits to hold values 0..x
+  return x <= 1 ? 1 : 1 + bits_for(x >> 1);
+}
+
+}  // namespace msa

@@ -1,0 +1,525 @@
+// msa_kernels.hip -- gfx950 kernels for the k-dimensional alignment DP.
+//
+// fill       : persistent tile-dataflow kernel.  Workgroups pop tiles from a
+//              queue ordered by computation wave (Section 3: partitions at
+//              equal distance from the origin are independent), wait for the
+//              k face-predecessor tiles, import the halo from HBM face
+//              planes, sweep the tile's local hyperplanes in LDS, export the
+//              tile's upper faces and its direction block, then publish a
+//              completion flag (agent-scope release / acquire).
+// traceback  : one wave walks the direction blocks from the far corner to the
+//              origin (Section 2), then expands the masks into gapped rows.
+// export     : decision tensor in row-major order (verification only).
+//
+// Per cell (Section 2 / Eq. 1 generalised; Section 4 per-cell steps): the
+// pair scores of the column, the 2^k - 1 lower neighbours, one candidate per
+// neighbour, the maximum.  Candidates are packed keys
+//     key = (score << k) | (2^k - 1 - b)
+// so one signed integer max yields the best score and, among equal scores,
+// the lowest neighbour mask b.  Stored scores keep the low k bits clear.
+#include <hip/hip_runtime.h>
+
+#include "msa_internal.h"
+
+namespace msa {
+
+enum { ST_OK = 0, ST_EINVAL = -1, ST_EDEVICE = -4 };
+
+template <int K>
+struct Cfg {
+  static constexpr int T = tile_edge_for_k(K);
+  static constexpr int E = T + 1;          // LDS edge including the halo
+  static constexpr int NS = ipow(E, K);    // LDS score cells
+  static constexpr int NC = ipow(T, K);    // cells of a full tile
+  static constexpr int NP = K * (K - 1) / 2;
+  static constexpr int B = bits_for(T - 1);
+  static constexpr int M = (1 << K) - 1;
+  static constexpr int H = K * (T - 1) + 1;  // hyperplanes of a full tile
+  static constexpr int DBS = (NC + 15) / 16 * 16;
+  static constexpr int sstride(int i) { return ipow(E, K - 1 - i); }
+  static constexpr int dstride(int i) { return ipow(T, K - 1 - i); }
+  static constexpr int pair_index(int i, int j) {  // i < j
+    return i * (2 * K - i - 1) / 2 + (j - i - 1);
+  }
+  static constexpr int off(int b) {  // LDS offset of neighbour v - b
+    int o = 0;
+    for (int i = 0; i < K; ++i)
+      if ((b >> i) & 1) o += sstride(i);
+    return o;
+  }
+};
+
+template <int K>
+struct Smem {
+  int32_t S[Cfg<K>::NS];
+  int32_t PT[Cfg<K>::NP * Cfg<K>::T * Cfg<K>::T];
+  int32_t HS[Cfg<K>::H + 1];
+  int32_t GK[K + 1];
+  uint8_t RES[K * Cfg<K>::T];
+  alignas(16) uint8_t DIRB[Cfg<K>::DBS];
+  int32_t bcast;
+};
+
+__device__ inline int64_t wall_now() { return (int64_t)wall_clock64(); }
+
+// Watchdog for dependency waits: wall_clock64 runs at a fixed 100 MHz.
+constexpr int64_t kWaitLimitTicks = 200000000;  // 2 s
+
+// ---------------------------------------------------------------------------
+// One tile of the fill.
+// ---------------------------------------------------------------------------
+template <int K, int NT>
+__device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
+                             Ctrl *ctrl, Smem<K> &sm) {
+  using C = Cfg<K>;
+  constexpr int T = C::T;
+  constexpr int E = C::E;
+  constexpr int M = C::M;
+  const int tid = threadIdx.x;
+
+  int c[K], lo[K], ext[K];
+  bool full = true, origin = true, corner = true;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    c[i] = (tile / jd.tstride[i]) % jd.P[i];
+    lo[i] = c[i] == 0 ? 0 : (c[i] - 1) * T + 1;
+    ext[i] = c[i] == 0 ? 1 : min(T, jd.n[i] - (c[i] - 1) * T);
+    full = full && ext[i] == T;
+    origin = origin && c[i] == 0;
+    corner = corner && c[i] == jd.P[i] - 1;
+  }
+
+  // ---- wait for the k face predecessors (diagonal ones are implied) ----
+  // Lane i polls the flag of tile c - e_i.  The loop condition is a wave vote
+  // and every exit test is wave-uniform, so the wave never splits here.
+  {
+    const int32_t *f = jd.flags;
+    bool need = false;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (tid == i && c[i] > 0) {
+        need = true;
+        f = jd.flags + (tile - jd.tstride[i]);
+      }
+    }
+    const int64_t t0 = wall_now();
+    for (;;) {
+      bool ok = true;
+      if (need) ok = __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+      if (__all(ok)) break;
+      const int st = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (st == ST_EDEVICE) break;
+      if (wall_now() - t0 > kWaitLimitTicks) {
+        atomicCAS(&ctrl->status, ST_OK, ST_EDEVICE);  // all lanes: idempotent
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+  // ---- residues of this tile (v = lo + q; sequence index v - 1) ----
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    for (int q = tid; q < T; q += NT) {
+      const int v = lo[i] + q;
+      int r = 0;
+      if (q < ext[i] && v >= 1) {
+        r = jd.seqs[jd.seq_off[i] + v - 1];
+        if (r >= alpha) {
+          atomicCAS(&ctrl->status, ST_OK, ST_EINVAL);
+          r = 0;
+        }
+      }
+      sm.RES[i * T + q] = (uint8_t)r;
+    }
+  }
+
+  // ---- halo: layer l_i = 0 along each dimension ----
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    constexpr int cnt = ipow(E, K - 1);
+    const int32_t *plane =
+        c[i] > 0 ? jd.faces + jd.face_off[i] + (int64_t)(c[i] - 1) * jd.fplane[i] : nullptr;
+    for (int idx = tid; idx < cnt; idx += NT) {
+      int rem = idx;
+      int sidx = 0;
+      bool valid = true, neg = (c[i] == 0);
+      int64_t foff = 0;
+#pragma unroll
+      for (int j = K - 1; j >= 0; --j) {
+        if (j == i) continue;
+        const int l = rem % E;
+        rem /= E;
+        valid = valid && l <= ext[j];
+        sidx += l * C::sstride(j);
+        const int v = lo[j] - 1 + l;
+        neg = neg || v < 0;
+        foff += (int64_t)v * jd.fstride[i][j];
+      }
+      if (valid) sm.S[sidx] = neg ? kNegKey : plane[foff];
+    }
+  }
+  __syncthreads();
+
+  // ---- pair tables: PT[p][a][b] = sub(r_i(a), r_j(b)) << k ----
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+#pragma unroll
+    for (int j = i + 1; j < K; ++j) {
+      constexpr int TT = T * T;
+      int32_t *pt = sm.PT + C::pair_index(i, j) * TT;
+      for (int idx = tid; idx < TT; idx += NT) {
+        const int a = sm.RES[i * T + idx / T];
+        const int b = sm.RES[j * T + idx % T];
+        pt[idx] = ((int32_t)jd.sub[a * alpha + b]) * (1 << K);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- sweep local hyperplanes ----
+  if (origin) {
+    // every lane writes the same values (no lane-divergent branch)
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) s += C::sstride(i);
+    sm.S[s] = 0;
+    sm.DIRB[0] = (uint8_t)M;  // decodes to mask 0
+  } else {
+    int hmax = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) hmax += ext[i] - 1;
+    int32_t gk[K + 1];
+#pragma unroll
+    for (int cbits = 0; cbits <= K; ++cbits) gk[cbits] = sm.GK[cbits];
+    for (int h = 0; h <= hmax; ++h) {
+      const int beg = __builtin_amdgcn_readfirstlane(sm.HS[h]);
+      const int end = __builtin_amdgcn_readfirstlane(sm.HS[h + 1]);
+      for (int e = beg + tid; e < end; e += NT) {
+        const uint32_t pk = jd.cells[e];
+        int q[K];
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          q[i] = (pk >> (i * C::B)) & ((1u << C::B) - 1);
+          ok = ok && (full || q[i] < ext[i]);
+        }
+        if (!ok) continue;
+        int sidx = 0, didx = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          sidx += (q[i] + 1) * C::sstride(i);
+          didx += q[i] * C::dstride(i);
+        }
+        int32_t pv[C::NP > 0 ? C::NP : 1];
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+          for (int j = i + 1; j < K; ++j)
+            pv[C::pair_index(i, j)] = sm.PT[C::pair_index(i, j) * T * T + q[i] * T + q[j]];
+        int32_t best = INT32_MIN;
+#pragma unroll
+        for (int b = 1; b <= M; ++b) {
+          int32_t cs = 0;
+#pragma unroll
+          for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = i + 1; j < K; ++j)
+              if (((b >> i) & 1) && ((b >> j) & 1)) cs += pv[C::pair_index(i, j)];
+          const int nb = __builtin_popcount(b);
+          const int32_t cand = sm.S[sidx - C::off(b)] + cs + gk[nb] + (M - b);
+          best = max(best, cand);
+        }
+        sm.S[sidx] = best & ~M;
+        sm.DIRB[didx] = (uint8_t)best;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+
+  if (corner) {  // all lanes store the same value
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) s += ext[i] * C::sstride(i);
+    *jd.score_out = (int64_t)(sm.S[s] >> K);
+  }
+
+  // ---- export upper faces (layer l_i = ext_i) for the successor along i ----
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    if (c[i] >= jd.P[i] - 1) continue;
+    constexpr int cnt = ipow(T, K - 1);
+    int32_t *plane = jd.faces + jd.face_off[i] + (int64_t)c[i] * jd.fplane[i];
+    for (int idx = tid; idx < cnt; idx += NT) {
+      int rem = idx;
+      int sidx = ext[i] * C::sstride(i);
+      bool valid = true;
+      int64_t foff = 0;
+#pragma unroll
+      for (int j = K - 1; j >= 0; --j) {
+        if (j == i) continue;
+        const int qq = rem % T;
+        rem /= T;
+        valid = valid && qq < ext[j];
+        sidx += (qq + 1) * C::sstride(j);
+        foff += (int64_t)(lo[j] + qq) * jd.fstride[i][j];
+      }
+      if (valid) plane[foff] = sm.S[sidx];
+    }
+  }
+
+  // ---- export the direction block (16 bytes per lane) ----
+  {
+    uint4 *dst = reinterpret_cast<uint4 *>(jd.dir + (int64_t)tile * C::DBS);
+    const uint4 *src = reinterpret_cast<const uint4 *>(sm.DIRB);
+    for (int idx = tid; idx < C::DBS / 16; idx += NT) dst[idx] = src[idx];
+  }
+
+  // ---- publish completion ----
+  // Every lane stores the same flag value: a lane-divergent branch next to the
+  // persistent loop's back edge lets the compiler peel lane 0 off the loop.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  __hip_atomic_store(jd.flags + tile, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int K>
+__device__ void load_job_tables(const JobDev &jd, int gap, Smem<K> &sm) {
+  using C = Cfg<K>;
+  for (int h = threadIdx.x; h <= C::H; h += blockDim.x) sm.HS[h] = jd.hstart[h];
+  if (threadIdx.x <= K) {
+    const int cb = threadIdx.x;
+    sm.GK[cb] = (gap * cb * (K - cb)) * (1 << K);
+  }
+}
+
+// Plain path: one job, descriptor passed by value.
+template <int K, int NT>
+__global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
+                                                  const int32_t *__restrict__ order) {
+  __shared__ Smem<K> sm;
+  const int alpha = ctrl->alpha;
+  load_job_tables<K>(jd, ctrl->gap, sm);
+  const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  static_assert(NT == 64, "one wave per workgroup: the pop below is per wave");
+  for (;;) {
+    // Queue pop without a lane-divergent branch: every lane issues the atomic,
+    // only lane 0 adds 1, and lane 0's result is broadcast as a wave-uniform
+    // (SGPR) value, so the loop exit below is uniform.
+    const int got = atomicAdd(&ctrl->head, threadIdx.x == 0 ? 1 : 0);
+    const int qi = __builtin_amdgcn_readfirstlane(got);
+    if (qi >= jd.ntiles) break;
+    process_tile<K, NT>(jd, alpha, __builtin_amdgcn_readfirstlane(order[qi]), epoch, ctrl, sm);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Traceback: one workgroup of one wave.
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ void traceback_job(const JobDev &jd, Ctrl *ctrl, uint8_t *dirb,
+                              int32_t *bc) {
+  using C = Cfg<K>;
+  constexpr int T = C::T;
+  constexpr int M = C::M;
+  const int tid = threadIdx.x;
+  const int NT = blockDim.x;
+  int status = __builtin_amdgcn_readfirstlane(
+      __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  int v[K];
+  bool done = true;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    v[i] = jd.n[i];
+    done = done && v[i] == 0;
+  }
+  int64_t L = 0;
+  if (status != ST_OK) done = true;
+  while (!done) {
+    int t = 0, q[K], d = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int ci = v[i] == 0 ? 0 : (v[i] - 1) / T + 1;
+      const int loi = ci == 0 ? 0 : (ci - 1) * T + 1;
+      t += ci * jd.tstride[i];
+      q[i] = v[i] - loi;
+      d += q[i] * C::dstride(i);
+    }
+    __syncthreads();
+    {
+      const uint4 *src = reinterpret_cast<const uint4 *>(jd.dir + (int64_t)t * C::DBS);
+      uint4 *dst = reinterpret_cast<uint4 *>(dirb);
+      for (int idx = tid; idx < C::DBS / 16; idx += NT) dst[idx] = src[idx];
+    }
+    __syncthreads();
+    for (;;) {
+      // every lane walks the same path: keep the walk state wave-uniform
+      const int byte = __builtin_amdgcn_readfirstlane(dirb[d]);
+      const int b = M - (byte & M);
+      bool bad = b == 0 || L >= jd.total_len;
+#pragma unroll
+      for (int i = 0; i < K; ++i) bad = bad || (((b >> i) & 1) && v[i] == 0);
+      if (bad) {  // corrupt decision data: never step outside the tensor
+        status = ST_EDEVICE;
+        done = true;
+        break;
+      }
+      jd.path[L] = (uint8_t)b;  // every lane stores the same byte
+      ++L;
+      bool all0 = true, leave = false;
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        if ((b >> i) & 1) {
+          v[i] -= 1;
+          q[i] -= 1;
+          d -= C::dstride(i);
+        }
+        all0 = all0 && v[i] == 0;
+        leave = leave || q[i] < 0;
+      }
+      if (all0) {
+        done = true;
+        break;
+      }
+      if (leave) break;
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  if (status != ST_OK) L = 0;
+
+  // expand masks (path[L-1] is the first column) into gapped rows
+  int cnt[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) cnt[i] = 0;
+  for (int64_t c0 = 0; c0 < L; c0 += NT) {
+    const int64_t col = c0 + tid;
+    const int m = col < L ? jd.path[L - 1 - col] : 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int bit = (m >> i) & 1;
+      // inclusive prefix sum over the workgroup (one wave)
+      int incl = bit;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(incl, d, 64);
+        if ((tid & 63) >= d) incl += y;
+      }
+      const int pos = cnt[i] + incl - bit;
+      if (col < L)
+        jd.aln_out[(int64_t)i * jd.aln_cap + col] =
+            bit ? jd.seqs[jd.seq_off[i] + pos] : (uint8_t)0xFF;
+      cnt[i] += __shfl(incl, 63, 64);
+    }
+  }
+  if (tid == 0) {
+    *jd.aln_len_out = L;
+    *jd.status_out = status;
+    if (status != ST_OK) *jd.score_out = 0;
+  }
+  (void)bc;
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void traceback_kernel(JobDev jd, Ctrl *ctrl) {
+  __shared__ alignas(16) uint8_t dirb[Cfg<K>::DBS];
+  __shared__ int32_t bc;
+  traceback_job<K>(jd, ctrl, dirb, &bc);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // ready the control block for the next launch on this workspace
+    ctrl->head = 0;
+    ctrl->status = ST_OK;
+    ctrl->epoch = ctrl->epoch + 1;
+  }
+}
+
+// Row-major decision tensor (mask b per cell) from the tile-major blocks.
+template <int K>
+__global__ void export_dirs_kernel(JobDev jd, uint8_t *out, int64_t ncell) {
+  using C = Cfg<K>;
+  constexpr int T = C::T;
+  for (int64_t lin = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; lin < ncell;
+       lin += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = lin;
+    int v[K];
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+      v[i] = (int)(rem % (jd.n[i] + 1));
+      rem /= (jd.n[i] + 1);
+    }
+    int t = 0, d = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int ci = v[i] == 0 ? 0 : (v[i] - 1) / T + 1;
+      const int loi = ci == 0 ? 0 : (ci - 1) * T + 1;
+      t += ci * jd.tstride[i];
+      d += (v[i] - loi) * C::dstride(i);
+    }
+    const int byte = jd.dir[(int64_t)t * C::DBS + d];
+    out[lin] = (uint8_t)(C::M - (byte & C::M));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (called from the ABI layer).
+// ---------------------------------------------------------------------------
+constexpr int kFillThreads = 64;
+
+template <int K>
+static int launch_plain_k(const JobDev &jd, Ctrl *ctrl, const int32_t *order,
+                          int grid, hipStream_t s) {
+  hipLaunchKernelGGL((fill_kernel<K, kFillThreads>), dim3(grid), dim3(kFillThreads), 0, s,
+                     jd, ctrl, order);
+  if (hipGetLastError() != hipSuccess) return -1;
+  hipLaunchKernelGGL((traceback_kernel<K>), dim3(1), dim3(64), 0, s, jd, ctrl);
+  if (hipGetLastError() != hipSuccess) return -1;
+  return 0;
+}
+
+template <int K>
+static int occupancy_k() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fill_kernel<K, kFillThreads>,
+                                                   kFillThreads, 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+template <int K>
+static int launch_export_k(const JobDev &jd, uint8_t *out, int64_t ncell, hipStream_t s) {
+  int64_t blocks = (ncell + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((export_dirs_kernel<K>), dim3((unsigned)blocks), dim3(256), 0, s, jd, out,
+                     ncell);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+#define MSA_DISPATCH_K(k, fn, ...)                 \
+  switch (k) {                                     \
+    case 2: return fn<2>(__VA_ARGS__);             \
+    case 3: return fn<3>(__VA_ARGS__);             \
+    case 4: return fn<4>(__VA_ARGS__);             \
+    case 5: return fn<5>(__VA_ARGS__);             \
+    case 6: return fn<6>(__VA_ARGS__);             \
+    case 7: return fn<7>(__VA_ARGS__);             \
+    case 8: return fn<8>(__VA_ARGS__);             \
+    default: return -1;                            \
+  }
+
+int launch_plain(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, hipStream_t s) {
+  MSA_DISPATCH_K(jd.k, launch_plain_k, jd, ctrl, order, grid, s);
+}
+
+int fill_occupancy(int k) { MSA_DISPATCH_K(k, occupancy_k); }
+
+int launch_export(const JobDev &jd, uint8_t *out, int64_t ncell, hipStream_t s) {
+  MSA_DISPATCH_K(jd.k, launch_export_k, jd, out, ncell, s);
+}
+
+}  // namespace msa

@@ -1,0 +1,208 @@
+// msa_plan.cpp -- host core of the library (no device calls).
+#include "msa_plan.h"
+
+#include <string.h>
+
+#include <algorithm>
+
+#include "../../include/msa_dp.h"
+
+namespace msa {
+
+static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+static bool mul_ok(int64_t a, int64_t b, int64_t lim) { return a == 0 || b <= lim / a; }
+
+int make_plan(const int32_t *lens, int32_t k, Plan *p) {
+  if (!lens || !p || k < 2 || k > kMaxK) return MSA_EINVAL;
+  Plan q;
+  q.k = k;
+  q.T = tile_edge_for_k(k);
+  const int64_t lim = (int64_t)1 << 50;
+  q.ncell = 1;
+  int64_t a = 1;
+  for (int i = 0; i < k; ++i) {
+    if (lens[i] < 0 || lens[i] > (1 << 24)) return MSA_EINVAL;
+    q.n[i] = lens[i];
+    q.P[i] = 1 + (lens[i] + q.T - 1) / q.T;
+    if (!mul_ok(q.ncell, (int64_t)lens[i] + 1, lim)) return MSA_ENOMEM;
+    q.ncell *= (int64_t)lens[i] + 1;
+    if (!mul_ok(a, 2 * (int64_t)lens[i] + 1, lim)) return MSA_ENOMEM;
+    a *= 2 * (int64_t)lens[i] + 1;
+    q.total_len += lens[i];
+  }
+  q.nu = a - q.ncell;
+  q.ntiles = 1;
+  for (int i = k - 1; i >= 0; --i) {
+    q.tstride[i] = (int32_t)q.ntiles;
+    if (!mul_ok(q.ntiles, q.P[i], kMaxTiles)) return MSA_ENOMEM;
+    q.ntiles *= q.P[i];
+  }
+  q.nwaves = 1 - k;
+  for (int i = 0; i < k; ++i) q.nwaves += q.P[i];
+  const int64_t nc = ipow(q.T, k);
+  q.ncells_table = (int32_t)nc;
+  q.H = k * (q.T - 1) + 1;
+  q.dbs = (int32_t)((nc + 15) / 16 * 16);
+  // face planes: dimension i keeps P_i - 1 planes over the other dimensions
+  q.face_elems = 0;
+  for (int i = 0; i < k; ++i) {
+    int64_t plane = 1;
+    for (int j = k - 1; j >= 0; --j) {
+      if (j == i) continue;
+      q.fstride[i][j] = plane;
+      if (!mul_ok(plane, (int64_t)q.n[j] + 1, lim)) return MSA_ENOMEM;
+      plane *= (int64_t)q.n[j] + 1;
+    }
+    q.fplane[i] = plane;
+    q.face_off[i] = q.face_elems;
+    if (!mul_ok(plane, (int64_t)q.P[i] - 1, lim)) return MSA_ENOMEM;
+    q.face_elems += plane * (q.P[i] - 1);
+  }
+  // workspace layout
+  int64_t o = 0;
+  q.off_ctrl = o;   o = align256(o + (int64_t)sizeof(Ctrl));
+  q.off_sub = o;    o = align256(o + kSubBytes);
+  q.off_cells = o;  o = align256(o + nc * 4);
+  q.off_hstart = o; o = align256(o + (int64_t)(q.H + 1) * 4);
+  q.off_order = o;  o = align256(o + q.ntiles * 4);
+  q.off_flags = o;  o = align256(o + q.ntiles * 4);
+  q.off_path = o;   o = align256(o + std::max<int64_t>(q.total_len, 1));
+  q.off_faces = o;
+  if (!mul_ok(q.face_elems, 4, lim)) return MSA_ENOMEM;
+  o = align256(o + q.face_elems * 4);
+  q.off_dir = o;
+  if (!mul_ok(q.ntiles, q.dbs, lim)) return MSA_ENOMEM;
+  o = align256(o + q.ntiles * q.dbs);
+  q.bytes = o;
+  *p = q;
+  return MSA_OK;
+}
+
+void make_cell_table(int k, int T, std::vector<uint32_t> *cells, std::vector<int32_t> *hstart) {
+  const int B = bits_for(T - 1);
+  const int64_t nc = ipow(T, k);
+  const int H = k * (T - 1) + 1;
+  std::vector<int32_t> count(H + 1, 0);
+  std::vector<int32_t> hs(H + 1, 0);
+  auto hsum = [&](int64_t lin) {
+    int s = 0;
+    for (int i = k - 1; i >= 0; --i) {
+      s += (int)(lin % T);
+      lin /= T;
+    }
+    return s;
+  };
+  for (int64_t lin = 0; lin < nc; ++lin) count[hsum(lin)]++;
+  hs[0] = 0;
+  for (int h = 0; h < H; ++h) hs[h + 1] = hs[h] + count[h];
+  std::vector<int32_t> fillpos(hs.begin(), hs.end());
+  cells->assign(nc, 0);
+  for (int64_t lin = 0; lin < nc; ++lin) {
+    int64_t rem = lin;
+    uint32_t pk = 0;
+    int s = 0;
+    for (int i = k - 1; i >= 0; --i) {
+      const int q = (int)(rem % T);
+      rem /= T;
+      pk |= (uint32_t)q << (i * B);
+      s += q;
+    }
+    (*cells)[fillpos[s]++] = pk;
+  }
+  *hstart = hs;
+}
+
+void make_tile_order(const Plan &p, std::vector<int32_t> *order) {
+  std::vector<int64_t> count(p.nwaves + 1, 0);
+  auto wave = [&](int64_t t) {
+    int s = 0;
+    for (int i = 0; i < p.k; ++i) s += (int)((t / p.tstride[i]) % p.P[i]);
+    return s;
+  };
+  for (int64_t t = 0; t < p.ntiles; ++t) count[wave(t) + 1]++;
+  for (int w = 0; w < p.nwaves; ++w) count[w + 1] += count[w];
+  order->assign(p.ntiles, 0);
+  for (int64_t t = 0; t < p.ntiles; ++t) (*order)[count[wave(t)]++] = (int32_t)t;
+}
+
+int score_bounds(const int32_t *lens, int32_t k, const int8_t *submat, int32_t alpha,
+                 int32_t gap, int64_t *lo, int64_t *hi) {
+  if (!lens || !submat || !lo || !hi || k < 2 || k > kMaxK || alpha < 1 || alpha > 255)
+    return MSA_EINVAL;
+  int64_t sum = 0;
+  for (int i = 0; i < k; ++i) {
+    if (lens[i] < 0) return MSA_EINVAL;
+    sum += lens[i];
+  }
+  int smax = -128, sabs = 0;
+  for (int i = 0; i < alpha * alpha; ++i) {
+    smax = std::max<int>(smax, submat[i]);
+    sabs = std::max<int>(sabs, submat[i] < 0 ? -submat[i] : submat[i]);
+  }
+  if (gap <= 0) {
+    *lo = (int64_t)gap * (k - 1) * sum;
+    int64_t pairs = 0;
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j) pairs += std::min(lens[i], lens[j]);
+    *hi = (int64_t)std::max(0, smax) * pairs;
+  } else {
+    const int64_t m = std::max<int64_t>(gap, sabs);
+    *hi = sum * (int64_t)(k * (k - 1) / 2) * m;
+    *lo = -*hi;
+  }
+  return MSA_OK;
+}
+
+int check_scoring(const int32_t *lens, int32_t k, const int8_t *submat, int32_t alpha,
+                  int32_t gap) {
+  if (!submat || alpha < 1 || alpha > 255) return MSA_EINVAL;
+  for (int a = 0; a < alpha; ++a)
+    for (int b = a + 1; b < alpha; ++b)
+      if (submat[a * alpha + b] != submat[b * alpha + a]) return MSA_EINVAL;
+  int64_t lo = 0, hi = 0;
+  int rc = score_bounds(lens, k, submat, alpha, gap, &lo, &hi);
+  if (rc) return rc;
+  // largest |column score|: C(k,2) * max(|gap|, max|sub|)
+  int sabs = 0;
+  for (int i = 0; i < alpha * alpha; ++i)
+    sabs = std::max<int>(sabs, submat[i] < 0 ? -submat[i] : submat[i]);
+  const int64_t g = gap < 0 ? -(int64_t)gap : gap;
+  const int64_t colmax = (int64_t)(k * (k - 1) / 2) * std::max<int64_t>(g, sabs);
+  const int64_t span = (lo < 0 ? -lo : lo) + (hi < 0 ? -hi : hi) + 2 * colmax + 1;
+  // keys are score * 2^k; the -infinity key is -2^30 (see kNegKey)
+  if (span > (((int64_t)1 << 30) >> k)) return MSA_ERANGE;
+  return MSA_OK;
+}
+
+void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd) {
+  memset(jd, 0, sizeof(*jd));
+  jd->k = p.k;
+  jd->T = p.T;
+  jd->alpha = alpha;
+  jd->gap = gap;
+  int32_t off = 0;
+  for (int i = 0; i < p.k; ++i) {
+    jd->n[i] = p.n[i];
+    jd->P[i] = p.P[i];
+    jd->tstride[i] = p.tstride[i];
+    jd->seq_off[i] = off;
+    off += p.n[i];
+    jd->face_off[i] = p.face_off[i];
+    jd->fplane[i] = p.fplane[i];
+    for (int j = 0; j < p.k; ++j) jd->fstride[i][j] = p.fstride[i][j];
+  }
+  jd->ntiles = (int32_t)p.ntiles;
+  jd->nwaves = p.nwaves;
+  jd->dbs = p.dbs;
+  jd->total_len = p.total_len;
+  jd->sub = reinterpret_cast<const int8_t *>(ws + p.off_sub);
+  jd->cells = reinterpret_cast<const uint32_t *>(ws + p.off_cells);
+  jd->hstart = reinterpret_cast<const int32_t *>(ws + p.off_hstart);
+  jd->faces = reinterpret_cast<int32_t *>(ws + p.off_faces);
+  jd->dir = reinterpret_cast<uint8_t *>(ws + p.off_dir);
+  jd->flags = reinterpret_cast<int32_t *>(ws + p.off_flags);
+  jd->path = reinterpret_cast<uint8_t *>(ws + p.off_path);
+}
+
+}  // namespace msa

@@ -1,0 +1,58 @@
+// msa_plan.h -- host core: validation, closed-form score bounds, tile grid,
+// hyperplane cell tables, tile schedule and workspace layout.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "msa_internal.h"
+
+namespace msa {
+
+// Validated shape + derived geometry of one alignment.
+struct Plan {
+  int k = 0, T = 0;
+  int32_t n[kMaxK] = {};
+  int32_t P[kMaxK] = {};
+  int32_t tstride[kMaxK] = {};
+  int64_t ntiles = 0;
+  int32_t nwaves = 0;
+  int32_t dbs = 0;
+  int64_t ncell = 0;         // prod(n_i + 1)
+  int64_t nu = 0;            // neighbour updates prod(2n_i+1) - prod(n_i+1)
+  int64_t total_len = 0;     // sum n_i
+  int64_t face_off[kMaxK] = {};
+  int64_t fplane[kMaxK] = {};
+  int64_t fstride[kMaxK][kMaxK] = {};
+  int64_t face_elems = 0;
+  // workspace layout (byte offsets from the workspace base)
+  int64_t off_ctrl = 0, off_sub = 0, off_cells = 0, off_hstart = 0, off_order = 0,
+          off_flags = 0, off_path = 0, off_faces = 0, off_dir = 0, bytes = 0;
+  int32_t ncells_table = 0;  // T^k
+  int32_t H = 0;             // hyperplanes of a full tile
+};
+
+constexpr int64_t kSubBytes = 255 * 255;
+constexpr int64_t kMaxTiles = (int64_t)1 << 30;
+
+// Fills geometry and layout; returns 0 or a negative status.
+int make_plan(const int32_t *lens, int32_t k, Plan *p);
+
+// Cell table (hyperplane-sorted packed coordinates) and hyperplane starts.
+void make_cell_table(int k, int T, std::vector<uint32_t> *cells, std::vector<int32_t> *hstart);
+
+// Tiles ordered by computation wave (sum of tile coordinates).
+void make_tile_order(const Plan &p, std::vector<int32_t> *order);
+
+// Validation of scoring inputs (matrix symmetric, alpha range) and the
+// device integer range check.  Returns 0 or a negative status.
+int check_scoring(const int32_t *lens, int32_t k, const int8_t *submat, int32_t alpha,
+                  int32_t gap);
+
+int score_bounds(const int32_t *lens, int32_t k, const int8_t *submat, int32_t alpha,
+                 int32_t gap, int64_t *lo, int64_t *hi);
+
+// Device descriptor for a plan placed at workspace base `ws`.
+void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd);
+
+}  // namespace msa

@@ -1,0 +1,92 @@
+// msa_runtime.cpp -- workspace set-up and plain-path launches.
+#include "msa_runtime.h"
+
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/msa_dp.h"
+
+namespace msa {
+
+namespace {
+std::mutex g_mu;
+int g_cu[64] = {};
+int g_occ[64][kMaxK + 1] = {};
+}  // namespace
+
+int device_cu_count() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_cu[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n < 1)
+      n = 1;
+    g_cu[dev] = n;
+  }
+  return g_cu[dev];
+}
+
+static int occupancy(int k) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_occ[dev][k]) g_occ[dev][k] = fill_occupancy(k);
+  return g_occ[dev][k] > 0 ? g_occ[dev][k] : 1;
+}
+
+int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, int gap,
+                      hipStream_t s) {
+  std::vector<uint32_t> cells;
+  std::vector<int32_t> hstart, order;
+  make_cell_table(p.k, p.T, &cells, &hstart);
+  make_tile_order(p, &order);
+  Ctrl ctrl;
+  memset(&ctrl, 0, sizeof(ctrl));
+  ctrl.epoch = 1;
+  ctrl.alpha = alpha;
+  ctrl.gap = gap;
+  bool ok = true;
+  ok = ok && hipMemcpyAsync(ws + p.off_ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, s) ==
+                 hipSuccess;
+  ok = ok && hipMemcpyAsync(ws + p.off_sub, submat, (size_t)alpha * alpha,
+                            hipMemcpyHostToDevice, s) == hipSuccess;
+  ok = ok && hipMemcpyAsync(ws + p.off_cells, cells.data(), cells.size() * 4,
+                            hipMemcpyHostToDevice, s) == hipSuccess;
+  ok = ok && hipMemcpyAsync(ws + p.off_hstart, hstart.data(), hstart.size() * 4,
+                            hipMemcpyHostToDevice, s) == hipSuccess;
+  ok = ok && hipMemcpyAsync(ws + p.off_order, order.data(), order.size() * 4,
+                            hipMemcpyHostToDevice, s) == hipSuccess;
+  ok = ok && hipMemsetAsync(ws + p.off_flags, 0, (size_t)p.ntiles * 4, s) == hipSuccess;
+  ok = ok && hipStreamSynchronize(s) == hipSuccess;
+  return ok ? MSA_OK : MSA_EDEVICE;
+}
+
+int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, uint8_t *d_aln,
+              int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s) {
+  JobDev jd;
+  fill_jobdev(p, ws, 0, 0, &jd);  // alpha and gap are read from the control block
+  jd.seqs = d_seqs;
+  jd.score_out = d_score;
+  jd.aln_out = d_aln;
+  jd.aln_cap = aln_cap;
+  jd.aln_len_out = d_aln_len;
+  jd.status_out = d_status;
+  int64_t grid = (int64_t)device_cu_count() * occupancy(p.k);
+  if (grid > p.ntiles) grid = p.ntiles;
+  if (grid < 1) grid = 1;
+  Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
+  const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
+  return launch_plain(jd, ctrl, order, (int)grid, s) == 0 ? MSA_OK : MSA_EDEVICE;
+}
+
+int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s) {
+  JobDev jd;
+  fill_jobdev(p, ws, 0, 0, &jd);
+  return launch_export(jd, out, p.ncell, s) == 0 ? MSA_OK : MSA_EDEVICE;
+}
+
+}  // namespace msa

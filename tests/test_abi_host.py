@@ -1,0 +1,124 @@
+"""Host-side tests of the C ABI (no GPU needed).
+
+- the shared library loads and exports every function declared in
+  include/msa_dp.h;
+- the tile-wave enumerator reproduces Table 1 and Table 2 and Eqs. 2-3;
+- the closed-form score bounds hold against the oracle;
+- argument validation rejects bad input before any device call.
+"""
+import re
+from math import comb
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import paper_2311_17530_amd as msa
+from msa_inputs import dna_scoring, protein_scoring
+from oracle import oracle_align
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def declared_functions():
+    text = (ROOT / "include" / "msa_dp.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(msa_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    lib = msa.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(msa.exported_names())
+
+
+def test_table1_partitions_per_wave():
+    # Table 1: unbounded shape, k = 2..9 sequences, waves 1..9; entries are
+    # C(w + k - 2, k - 1).  A grid with >= 9 tiles per dimension is unbounded
+    # for the first 9 waves.
+    table1 = {
+        2: [1, 2, 3, 4, 5, 6, 7, 8, 9],
+        3: [1, 3, 6, 10, 15, 21, 28, 36, 45],
+        4: [1, 4, 10, 20, 35, 56, 84, 120, 165],
+        5: [1, 5, 15, 35, 70, 126, 210, 330, 495],
+        6: [1, 6, 21, 56, 126, 252, 462, 792, 1287],
+        7: [1, 7, 28, 84, 210, 462, 924, 1716, 3003],
+        8: [1, 8, 36, 120, 330, 792, 1716, 3432, 6435],
+    }
+    for k, row in table1.items():
+        counts = msa.wave_counts([9] * k)
+        assert counts[:9] == row
+        assert row == [comb(w + k - 2, k - 1) for w in range(1, 10)]
+
+
+def test_table2_shape_9999_s3():
+    # Table 2: shape (9,9,9,9), partition size S = 3 -> p_i = (9-1)/(3-1) = 4
+    # per dimension (Eq. 3), 256 partitions in 13 waves (Eq. 2).
+    counts = msa.wave_counts([4, 4, 4, 4])
+    assert counts == [1, 4, 10, 20, 31, 40, 44, 40, 31, 20, 10, 4, 1]
+    assert sum(counts) == 256  # Eq. 3: prod p_i
+    assert len(counts) == 4 + 3 * (4 - 1)  # Eq. 2: p_0 + sum_{i>=1}(p_i - 1)
+    assert 9 ** 4 == 6561
+
+
+def test_library_tile_grid_matches_eq2_eq3():
+    # the library's own grid adds the one-cell v_i = 0 layer to the paper's
+    # p_i = n_i / T partitions; with that layer removed Eqs. 2-3 hold exactly
+    for k in (2, 3, 4, 5):
+        T = msa.tile_edge(k)
+        lens = [T * m for m in range(1, k + 1)]
+        P, waves = msa.tile_grid(lens, T)
+        assert P == [1 + n // T for n in lens]
+        assert waves == sum(P) - k + 1
+        inner = [p - 1 for p in P]
+        assert sum(msa.wave_counts(inner)) == int(np.prod(inner))
+        assert len(msa.wave_counts(inner)) == inner[0] + sum(p - 1 for p in inner[1:])
+
+
+def test_score_bounds_hold():
+    rng = np.random.Generator(np.random.PCG64(3))
+    for _ in range(30):
+        k = int(rng.integers(2, 5))
+        sub, gap = (dna_scoring() if rng.integers(0, 2) else protein_scoring())
+        alpha = sub.shape[0]
+        seqs = [rng.integers(0, alpha, size=int(rng.integers(0, 9))).astype(np.uint8)
+                for _ in range(k)]
+        lo, hi = msa.score_bounds([len(s) for s in seqs], sub, gap)
+        s, _, _ = oracle_align(seqs, sub, gap)
+        assert lo <= s <= hi
+
+
+def test_validation_rejects_before_device():
+    sub, gap = dna_scoring()
+    a = np.array([0, 1, 2], np.uint8)
+    with pytest.raises(msa.MsaError) as e:
+        msa.align([a], sub, gap)  # k < 2
+    assert e.value.status == msa.MSA_EINVAL
+    with pytest.raises(msa.MsaError) as e:
+        msa.align([a] * 9, sub, gap)  # k > MAX_K
+    assert e.value.status == msa.MSA_EINVAL
+    with pytest.raises(msa.MsaError) as e:
+        msa.align([a, np.array([4], np.uint8)], sub, gap)  # code >= alpha
+    assert e.value.status == msa.MSA_EINVAL
+    asym = sub.copy()
+    asym[0, 1] = 5
+    with pytest.raises(msa.MsaError) as e:
+        msa.align([a, a], asym, gap)  # asymmetric matrix
+    assert e.value.status == msa.MSA_EINVAL
+    big = np.full((4, 4), 127, np.int8)
+    with pytest.raises(msa.MsaError) as e:
+        msa.align([np.zeros(200000, np.uint8)] * 8, big, -128)  # range check
+    assert e.value.status in (msa.MSA_ERANGE, msa.MSA_ENOMEM)
+
+
+def test_workspace_bytes_and_errors():
+    assert msa.workspace_bytes([40, 40, 40]) > 41 ** 3
+    with pytest.raises(msa.MsaError):
+        msa.workspace_bytes([3])
+    with pytest.raises(msa.MsaError):
+        msa.workspace_bytes([3, -1])
+    assert msa.strerror(msa.MSA_ERANGE).startswith("score range")
