@@ -1,0 +1,154 @@
+"""Benchmark of the k-D DP alignment hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+A step is one whole alignment of the k=3 protein workload (three sequences of
+length 512, 513^3 cells): the fill (every cell, one direction byte per cell)
+followed by the traceback and the expansion of the gapped rows, with inputs
+already resident in HBM.  Prints one JSON line:
+
+  value        GCUPS = cells / step time / 1e9 (whole step, fill + traceback)
+  roofline     dominant kernel (the fill): algorithmic integer ops per launch
+               (2 per neighbour update: one add, one max) / its average launch
+               time measured with HIP events on its stream, against the int32
+               VALU peak 256 CU * 64 lanes * 2.4 GHz
+  cpu_baseline the oracle (plain single-threaded C) timed on this host on the
+               full k=3 / 512 alignment
+
+The same numbers for the k=4 / 128 workload (129^4 cells) are reported under
+"extra".  Only one GPU is used: --gpus above 1 is rejected.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.3 T int32 lane-ops/s
+PEAK_HBM_GBS = 8000.0
+MAIN = "prot_k3_512"
+EXTRA = ["prot_k4_128"]
+
+
+def time_workload(name, steps, warmup):
+    import torch
+    import paper_2311_17530_amd as msa
+    from msa_inputs import workload
+
+    job = workload(name)
+    dev = msa.DeviceAligner(job.lens, job.sub, job.gap)
+    dev.set_sequences(job.seqs)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        dev.run()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1, e2 in ev:
+        e0.record(stream)
+        dev.run_fill()
+        e1.record(stream)
+        dev.run_traceback()
+        e2.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fill_ms = [a.elapsed_time(b) for a, b, _ in ev]
+    tb_ms = [b.elapsed_time(c) for _, b, c in ev]
+    score, rows = dev.result()
+    ms_per_step = wall * 1e3 / steps
+    cells = job.cells
+    nu = job.neighbour_updates
+    fill_avg = float(np.mean(fill_ms))
+    return dict(
+        workload=name, k=job.k, lens=job.lens, cells=cells, neighbour_updates=nu,
+        ms_per_step=ms_per_step, fill_ms_avg=fill_avg, fill_ms_min=float(np.min(fill_ms)),
+        traceback_ms_avg=float(np.mean(tb_ms)),
+        gcups=cells / (ms_per_step / 1e3) / 1e9,
+        fill_gcups=cells / (fill_avg / 1e3) / 1e9,
+        nu_per_s=nu / (ms_per_step / 1e3),
+        fill_tops=2 * nu / (fill_avg / 1e3) / 1e12,
+        score=score, aln_len=int(rows.shape[1]),
+        tile_edge=msa.tile_edge(job.k))
+
+
+def cpu_baseline():
+    from msa_inputs import workload
+    from oracle import build_oracle_lib, oracle_align
+
+    build_oracle_lib(force=False)
+    job = workload(MAIN)
+    t0 = time.perf_counter()
+    oracle_align(job.seqs, job.sub, job.gap)
+    dt = time.perf_counter() - t0
+    return {"value": job.cells / dt / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
+            "sample": f"one full {MAIN} alignment (fill + traceback, "
+                      f"{job.cells} cells) in {dt:.2f} s, single thread, gcc -O2"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs each alignment on a "
+              "single MI355X and has no multi-GPU path (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    main_r = time_workload(MAIN, a.steps, a.warmup)
+    extra = {}
+    if not a.no_extra:
+        for name in EXTRA:
+            extra[name] = time_workload(name, a.steps, a.warmup)
+    achieved = main_r["fill_tops"]
+    line = {
+        "metric": "GCUPS",
+        "value": round(main_r["gcups"], 3),
+        "unit": "Gcell/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(main_r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": MAIN, "k": 3, "lens": main_r["lens"],
+                   "cells": main_r["cells"], "neighbour_updates": main_r["neighbour_updates"],
+                   "tile_edge": main_r["tile_edge"], "scoring": "20x20 int8 seed 17, gap -8"},
+        "neighbour_updates_per_s": main_r["nu_per_s"],
+        "fill_ms": round(main_r["fill_ms_avg"], 4),
+        "traceback_ms": round(main_r["traceback_ms_avg"], 4),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(PEAK_INT32_TOPS, 2), "unit": "Tops/s",
+                     "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
+                     "kernel": "fill_kernel<3,64>",
+                     "ops_per_launch": 2 * main_r["neighbour_updates"]},
+        "extra": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                      for kk, vv in v.items()} for k, v in extra.items()},
+    }
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -114,6 +114,19 @@ int msa_dp_align_dev(void *d_workspace, int64_t ws_bytes,
                      int64_t *d_score, uint8_t *d_aln, int64_t aln_cap,
                      int64_t *d_aln_len, int32_t *d_status, void *hip_stream);
 
+/* The two launches of msa_dp_align_dev, for callers that time or overlap them
+ * separately.  msa_dp_fill_dev scores every cell and writes the optimal score
+ * to d_score; msa_dp_traceback_dev then writes the alignment, its length and
+ * the status (and resets d_score to 0 on error).  Same arguments and rules as
+ * msa_dp_align_dev; the traceback must follow the fill on the same stream. */
+int msa_dp_fill_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
+                    const int32_t *lens, int32_t k, int64_t *d_score, void *hip_stream);
+
+int msa_dp_traceback_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
+                         const int32_t *lens, int32_t k, int64_t *d_score,
+                         uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len,
+                         int32_t *d_status, void *hip_stream);
+
 /* Copy the decision tensor of the last alignment run on `d_workspace` into
  * d_dir_out: prod(lens[i] + 1) bytes, row-major with the last sequence's
  * index fastest, byte = chosen neighbour mask b (0 at the origin).  For

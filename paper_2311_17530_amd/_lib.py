@@ -12,8 +12,11 @@ from pathlib import Path
 
 import numpy as np
 
+import os
+
 PKG = Path(__file__).resolve().parent
-LIB_PATH = PKG / "_lib" / "libmsa_dp.so"
+# MSA_LIB overrides the library path (a variant built with extra flags)
+LIB_PATH = Path(os.environ.get("MSA_LIB", str(PKG / "_lib" / "libmsa_dp.so")))
 
 MAX_K = 8
 GAP = 0xFF
@@ -62,6 +65,11 @@ _SIGS = {
                                       ctypes.c_int32, ctypes.c_int32, c_vp]),
     "msa_dp_align_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p, ctypes.c_int32,
                                         c_vp, c_vp, ctypes.c_int64, c_vp, c_vp, c_vp]),
+    "msa_dp_fill_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p, ctypes.c_int32,
+                                       c_vp, c_vp]),
+    "msa_dp_traceback_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p,
+                                            ctypes.c_int32, c_vp, c_vp, ctypes.c_int64, c_vp,
+                                            c_vp, c_vp]),
     "msa_dp_export_dirs": (ctypes.c_int, [c_vp, ctypes.c_int64, c_i32p, ctypes.c_int32,
                                           c_vp, c_vp]),
     "msa_dp_align_batch": (ctypes.c_int, [ctypes.POINTER(MsaJob), ctypes.c_int32,
@@ -223,6 +231,19 @@ class DeviceAligner:
                                     self.d_aln.data_ptr(), self.cap, self.d_len.data_ptr(),
                                     self.d_status.data_ptr(), self._stream())
         _check(rc, "msa_dp_align_dev")
+
+    def run_fill(self):
+        rc = lib().msa_dp_fill_dev(self.ws_ptr, self.ws_bytes, self.d_seqs.data_ptr(),
+                                   _i32arr(self.lens), self.k, self.d_score.data_ptr(),
+                                   self._stream())
+        _check(rc, "msa_dp_fill_dev")
+
+    def run_traceback(self):
+        rc = lib().msa_dp_traceback_dev(self.ws_ptr, self.ws_bytes, self.d_seqs.data_ptr(),
+                                        _i32arr(self.lens), self.k, self.d_score.data_ptr(),
+                                        self.d_aln.data_ptr(), self.cap, self.d_len.data_ptr(),
+                                        self.d_status.data_ptr(), self._stream())
+        _check(rc, "msa_dp_traceback_dev")
 
     def result(self):
         """Synchronise and return ``(score, rows)`` (raises on device status)."""

@@ -31,10 +31,10 @@ SOURCES = ["msa_kernels.hip", "msa_batch_kernels.hip", "msa_plan.cpp",
            "msa_runtime.cpp", "msa_abi.cpp", "msa_batch.cpp", "msa_server.cpp"]
 
 
-def _compile(src: Path, obj: Path) -> None:
-    cmd = [HIPCC, *COMMON, "-c", str(src), "-o", str(obj)]
+def _compile(src: Path, obj: Path, extra=()) -> None:
+    cmd = [HIPCC, *COMMON, *extra, "-c", str(src), "-o", str(obj)]
     if src.suffix == ".cpp":
-        cmd = [HIPCC, *COMMON, "-x", "hip", "-c", str(src), "-o", str(obj)]
+        cmd = [HIPCC, *COMMON, *extra, "-x", "hip", "-c", str(src), "-o", str(obj)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -47,28 +47,34 @@ def _compile(src: Path, obj: Path) -> None:
             sys.stderr.write("\n".join(lines) + "\n")
 
 
-def build_library(jobs: int | None = None) -> Path:
-    """Compile and link the library; returns the path of the shared object."""
-    bdir = PKG / "_build"
+def build_library(jobs: int | None = None, extra_flags=(), out: Path | None = None) -> Path:
+    """Compile and link the library; returns the path of the shared object.
+
+    ``extra_flags`` (e.g. ``["-DMSA_TRACE"]``) and ``out`` build a variant
+    elsewhere without touching the default library."""
+    out = Path(out) if out else LIB
+    tag = "" if out == LIB else "_" + out.stem
+    bdir = PKG / ("_build" + tag)
     bdir.mkdir(exist_ok=True)
-    OUT_DIR.mkdir(exist_ok=True)
+    out.parent.mkdir(parents=True, exist_ok=True)
     srcs = [CSRC / s for s in SOURCES if (CSRC / s).exists()]
     objs = [bdir / (s.name + ".o") for s in srcs]
     with cf.ThreadPoolExecutor(max_workers=jobs or min(8, len(srcs))) as ex:
-        list(ex.map(lambda a: _compile(*a), zip(srcs, objs)))
-    tmp = LIB.with_suffix(f".so.tmp{os.getpid()}")
+        list(ex.map(lambda a: _compile(*a, extra_flags), zip(srcs, objs)))
+    tmp = out.with_suffix(f".so.tmp{os.getpid()}")
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", str(tmp),
            *map(str, objs), "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link failed")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 def clean() -> None:
-    shutil.rmtree(PKG / "_build", ignore_errors=True)
+    for d in PKG.glob("_build*"):
+        shutil.rmtree(d, ignore_errors=True)
 
 
 if __name__ == "__main__":

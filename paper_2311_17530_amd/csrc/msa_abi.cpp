@@ -119,6 +119,38 @@ extern "C" int msa_dp_align_dev(void *d_workspace, int64_t ws_bytes, const uint8
                    d_status, (hipStream_t)hip_stream);
 }
 
+extern "C" int msa_dp_fill_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
+                               const int32_t *lens, int32_t k, int64_t *d_score,
+                               void *hip_stream) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255) || !d_score) return MSA_EINVAL;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  if (ws_bytes < p.bytes || (p.total_len > 0 && !d_seqs)) return MSA_EINVAL;
+  return run_plain(p, (char *)d_workspace, d_seqs, d_score, nullptr, 0, nullptr, nullptr,
+                   (hipStream_t)hip_stream, 1);
+}
+
+extern "C" int msa_dp_traceback_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
+                                    const int32_t *lens, int32_t k, int64_t *d_score,
+                                    uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len,
+                                    int32_t *d_status, void *hip_stream) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255) || !d_score || !d_aln_len || !d_status)
+    return MSA_EINVAL;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  if (ws_bytes < p.bytes || aln_cap < p.total_len || (p.total_len > 0 && !d_aln) ||
+      (p.total_len > 0 && !d_seqs))
+    return MSA_EINVAL;
+  return run_plain(p, (char *)d_workspace, d_seqs, d_score, d_aln, aln_cap, d_aln_len,
+                   d_status, (hipStream_t)hip_stream, 2);
+}
+
 extern "C" int msa_dp_export_dirs(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
                                   int32_t k, uint8_t *d_dir_out, void *hip_stream) {
   int rc = validate_shape(lens, k);

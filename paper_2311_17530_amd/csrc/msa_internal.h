@@ -49,6 +49,7 @@ struct JobDev {
   int64_t aln_cap;
   int64_t *aln_len_out;
   int32_t *status_out;
+  int64_t *trace;             // optional per-tile phase timestamps (debug builds)
 };
 
 // Control block of one persistent launch (in device memory).

@@ -6,7 +6,7 @@
 //              k face-predecessor tiles, import the halo from HBM face
 //              planes, sweep the tile's local hyperplanes in LDS, export the
 //              tile's upper faces and its direction block, then publish a
-//              completion flag (agent-scope release / acquire).
+//              completion flag.
 // traceback  : one wave walks the direction blocks from the far corner to the
 //              origin (Section 2), then expands the masks into gapped rows.
 // export     : decision tensor in row-major order (verification only).
@@ -18,6 +18,7 @@
 // so one signed integer max yields the best score and, among equal scores,
 // the lowest neighbour mask b.  Stored scores keep the low k bits clear.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 
 #include "msa_internal.h"
 
@@ -25,18 +26,27 @@ namespace msa {
 
 enum { ST_OK = 0, ST_EINVAL = -1, ST_EDEVICE = -4 };
 
+constexpr int kSubLds = 32;  // substitution matrices up to 32x32 live in LDS
+
 template <int K>
 struct Cfg {
   static constexpr int T = tile_edge_for_k(K);
   static constexpr int E = T + 1;          // LDS edge including the halo
-  static constexpr int NS = ipow(E, K);    // LDS score cells
+  // Row pitch of the LDS tile, padded to an even number of words: cells that
+  // are neighbours on a hyperplane (one step up in one dimension, one step down
+  // in the last) then differ by an odd number of words, so a wave reading
+  // them spreads over all LDS banks.
+  static constexpr int RP = (E % 2 == 0) ? E : E + 1;
+  static constexpr int NS = (K == 1 ? 1 : ipow(E, K - 2) * RP) * E;  // LDS score words
   static constexpr int NC = ipow(T, K);    // cells of a full tile
   static constexpr int NP = K * (K - 1) / 2;
   static constexpr int B = bits_for(T - 1);
   static constexpr int M = (1 << K) - 1;
   static constexpr int H = K * (T - 1) + 1;  // hyperplanes of a full tile
   static constexpr int DBS = (NC + 15) / 16 * 16;
-  static constexpr int sstride(int i) { return ipow(E, K - 1 - i); }
+  static constexpr int sstride(int i) {  // LDS strides: 1, RP, RP*E, RP*E^2, ...
+    return i == K - 1 ? 1 : RP * ipow(E, K - 2 - i);
+  }
   static constexpr int dstride(int i) { return ipow(T, K - 1 - i); }
   static constexpr int pair_index(int i, int j) {  // i < j
     return i * (2 * K - i - 1) / 2 + (j - i - 1);
@@ -51,24 +61,69 @@ struct Cfg {
 
 template <int K>
 struct Smem {
-  int32_t S[Cfg<K>::NS];
-  int32_t PT[Cfg<K>::NP * Cfg<K>::T * Cfg<K>::T];
-  int32_t HS[Cfg<K>::H + 1];
-  int32_t GK[K + 1];
-  uint8_t RES[K * Cfg<K>::T];
-  alignas(16) uint8_t DIRB[Cfg<K>::DBS];
-  int32_t bcast;
+  int32_t S[Cfg<K>::NS];                          // tile keys with halo
+  int32_t PT[Cfg<K>::NP * Cfg<K>::T * Cfg<K>::T];  // pair scores << k
+  int32_t SUB[kSubLds * kSubLds];                 // substitution matrix << k
+  uint16_t CELLS[Cfg<K>::NC];                     // hyperplane-sorted cells
+  int32_t HS[Cfg<K>::H + 1];                      // hyperplane starts
+  int32_t GK[K + 1];                              // gap term per |b|, << k
+  uint8_t RES[K * Cfg<K>::T];                     // residues of the tile
+  alignas(16) uint8_t DIRB[Cfg<K>::DBS];          // direction bytes
 };
 
 __device__ inline int64_t wall_now() { return (int64_t)wall_clock64(); }
 
+// Optional phase timestamps per tile (compile with -DMSA_TRACE): 8 int64 per
+// tile, written by every lane of the wave (same value, no divergent branch).
+#ifdef MSA_TRACE
+#define MSA_TRACE_POINT(jd, tile, j) \
+  do { if ((jd).trace) (jd).trace[(int64_t)(tile) * 8 + (j)] = wall_now(); } while (0)
+#else
+#define MSA_TRACE_POINT(jd, tile, j) do { } while (0)
+#endif
+
 // Watchdog for dependency waits: wall_clock64 runs at a fixed 100 MHz.
 constexpr int64_t kWaitLimitTicks = 200000000;  // 2 s
+
+// Face-plane accesses and completion flags.
+//  SYNC 1: plain face loads/stores, agent-scope release fence before the flag,
+//          agent-scope acquire fence after the wait (C++ memory model).
+//  SYNC 2: face values are relaxed agent-scope atomics (device-coherent
+//          loads/stores, no cache write-back or invalidate); the flag is
+//          stored only after the wave's face stores have completed.
+template <int SYNC>
+__device__ inline int32_t face_load(const int32_t *p) {
+  if constexpr (SYNC == 2)
+    return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  else
+    return *p;
+}
+template <int SYNC>
+__device__ inline void face_store(int32_t *p, int32_t v) {
+  if constexpr (SYNC == 2)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+
+// Per-launch constant tables into LDS (done once per persistent workgroup).
+template <int K, int NT>
+__device__ void load_tables(const JobDev &jd, int alpha, int gap, Smem<K> &sm) {
+  using C = Cfg<K>;
+  const int tid = threadIdx.x;
+  for (int h = tid; h <= C::H; h += NT) sm.HS[h] = jd.hstart[h];
+  for (int e = tid; e < C::NC; e += NT) sm.CELLS[e] = (uint16_t)jd.cells[e];
+  if (tid <= K) sm.GK[tid] = (gap * tid * (K - tid)) * (1 << K);
+  if (alpha <= kSubLds)
+    for (int e = tid; e < alpha * alpha; e += NT)
+      sm.SUB[(e / alpha) * kSubLds + e % alpha] = ((int32_t)jd.sub[e]) * (1 << K);
+}
 
 // ---------------------------------------------------------------------------
 // One tile of the fill.
 // ---------------------------------------------------------------------------
-template <int K, int NT>
+template <int K, int NT, int SYNC>
 __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
                              Ctrl *ctrl, Smem<K> &sm) {
   using C = Cfg<K>;
@@ -103,9 +158,10 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
       }
     }
     const int64_t t0 = wall_now();
+    MSA_TRACE_POINT(jd, tile, 0);
     for (;;) {
       bool ok = true;
-      if (need) ok = __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+      if (need) ok = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
       if (__all(ok)) break;
       const int st = __builtin_amdgcn_readfirstlane(
           __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -114,16 +170,20 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
         atomicCAS(&ctrl->status, ST_OK, ST_EDEVICE);  // all lanes: idempotent
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
   }
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if constexpr (SYNC != 2)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  else
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 
+  MSA_TRACE_POINT(jd, tile, 1);
   // ---- residues of this tile (v = lo + q; sequence index v - 1) ----
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    for (int q = tid; q < T; q += NT) {
+    if (tid < T) {
+      const int q = tid;
       const int v = lo[i] + q;
       int r = 0;
       if (q < ext[i] && v >= 1) {
@@ -138,32 +198,57 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
   }
 
   // ---- halo: layer l_i = 0 along each dimension ----
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
+  // Loads first, LDS stores after: for small k every face load of every
+  // dimension is in flight at once (one memory round trip per tile).
+  {
     constexpr int cnt = ipow(E, K - 1);
-    const int32_t *plane =
-        c[i] > 0 ? jd.faces + jd.face_off[i] + (int64_t)(c[i] - 1) * jd.fplane[i] : nullptr;
-    for (int idx = tid; idx < cnt; idx += NT) {
-      int rem = idx;
-      int sidx = 0;
-      bool valid = true, neg = (c[i] == 0);
-      int64_t foff = 0;
+    constexpr int IT = (cnt + NT - 1) / NT;
+    constexpr bool ALL = K * IT <= 48;
+    constexpr int CH = ALL ? IT : (IT < 6 ? IT : 6);
+    constexpr int DG = ALL ? K : 1;  // dimensions per pass
+    for (int i0 = 0; i0 < K; i0 += DG) {
+      for (int it0 = 0; it0 < IT; it0 += CH) {
+        int32_t val[DG][CH];
+        int sidx[DG][CH];
 #pragma unroll
-      for (int j = K - 1; j >= 0; --j) {
-        if (j == i) continue;
-        const int l = rem % E;
-        rem /= E;
-        valid = valid && l <= ext[j];
-        sidx += l * C::sstride(j);
-        const int v = lo[j] - 1 + l;
-        neg = neg || v < 0;
-        foff += (int64_t)v * jd.fstride[i][j];
+        for (int di = 0; di < DG; ++di) {
+          const int i = i0 + di;
+          const int32_t *plane =
+              c[i] > 0 ? jd.faces + jd.face_off[i] + (int64_t)(c[i] - 1) * jd.fplane[i]
+                       : jd.faces;
+#pragma unroll
+          for (int it = 0; it < CH; ++it) {
+            const int idx = tid + (it0 + it) * NT;
+            int rem = idx;
+            int s = 0;
+            bool valid = idx < cnt, neg = (c[i] == 0);
+            int64_t foff = 0;
+#pragma unroll
+            for (int j = K - 1; j >= 0; --j) {
+              if (j == i) continue;
+              const int l = rem % E;
+              rem /= E;
+              valid = valid && l <= ext[j];
+              s += l * C::sstride(j);
+              const int v = lo[j] - 1 + l;
+              neg = neg || v < 0;
+              foff += (int64_t)v * jd.fstride[i][j];
+            }
+            sidx[di][it] = valid ? s : -1;
+            val[di][it] = (valid && !neg) ? face_load<SYNC>(plane + foff) : kNegKey;
+          }
+        }
+#pragma unroll
+        for (int di = 0; di < DG; ++di)
+#pragma unroll
+          for (int it = 0; it < CH; ++it)
+            if (sidx[di][it] >= 0) sm.S[sidx[di][it]] = val[di][it];
       }
-      if (valid) sm.S[sidx] = neg ? kNegKey : plane[foff];
     }
   }
   __syncthreads();
 
+  MSA_TRACE_POINT(jd, tile, 2);
   // ---- pair tables: PT[p][a][b] = sub(r_i(a), r_j(b)) << k ----
 #pragma unroll
   for (int i = 0; i < K; ++i) {
@@ -174,12 +259,14 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
       for (int idx = tid; idx < TT; idx += NT) {
         const int a = sm.RES[i * T + idx / T];
         const int b = sm.RES[j * T + idx % T];
-        pt[idx] = ((int32_t)jd.sub[a * alpha + b]) * (1 << K);
+        pt[idx] = alpha <= kSubLds ? sm.SUB[a * kSubLds + b]
+                                   : ((int32_t)jd.sub[a * alpha + b]) * (1 << K);
       }
     }
   }
   __syncthreads();
 
+  MSA_TRACE_POINT(jd, tile, 3);
   // ---- sweep local hyperplanes ----
   if (origin) {
     // every lane writes the same values (no lane-divergent branch)
@@ -194,12 +281,12 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
     for (int i = 0; i < K; ++i) hmax += ext[i] - 1;
     int32_t gk[K + 1];
 #pragma unroll
-    for (int cbits = 0; cbits <= K; ++cbits) gk[cbits] = sm.GK[cbits];
+    for (int cb = 0; cb <= K; ++cb) gk[cb] = sm.GK[cb];
     for (int h = 0; h <= hmax; ++h) {
       const int beg = __builtin_amdgcn_readfirstlane(sm.HS[h]);
       const int end = __builtin_amdgcn_readfirstlane(sm.HS[h + 1]);
       for (int e = beg + tid; e < end; e += NT) {
-        const uint32_t pk = jd.cells[e];
+        const uint32_t pk = sm.CELLS[e];
         int q[K];
         bool ok = true;
 #pragma unroll
@@ -241,6 +328,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
   }
   __syncthreads();
 
+  MSA_TRACE_POINT(jd, tile, 4);
   if (corner) {  // all lanes store the same value
     int s = 0;
 #pragma unroll
@@ -268,7 +356,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
         sidx += (qq + 1) * C::sstride(j);
         foff += (int64_t)(lo[j] + qq) * jd.fstride[i][j];
       }
-      if (valid) plane[foff] = sm.S[sidx];
+      if (valid) face_store<SYNC>(plane + foff, sm.S[sidx]);
     }
   }
 
@@ -279,31 +367,32 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
     for (int idx = tid; idx < C::DBS / 16; idx += NT) dst[idx] = src[idx];
   }
 
+  MSA_TRACE_POINT(jd, tile, 5);
   // ---- publish completion ----
   // Every lane stores the same flag value: a lane-divergent branch next to the
   // persistent loop's back edge lets the compiler peel lane 0 off the loop.
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  __hip_atomic_store(jd.flags + tile, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <int K>
-__device__ void load_job_tables(const JobDev &jd, int gap, Smem<K> &sm) {
-  using C = Cfg<K>;
-  for (int h = threadIdx.x; h <= C::H; h += blockDim.x) sm.HS[h] = jd.hstart[h];
-  if (threadIdx.x <= K) {
-    const int cb = threadIdx.x;
-    sm.GK[cb] = (gap * cb * (K - cb)) * (1 << K);
+  if constexpr (SYNC == 1) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  } else {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);  // the wave's face stores have completed
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }
+  __syncthreads();
+  __hip_atomic_store(jd.flags + tile, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  MSA_TRACE_POINT(jd, tile, 6);
+#ifdef MSA_TRACE
+  if (jd.trace) jd.trace[(int64_t)tile * 8 + 7] = blockIdx.x;
+#endif
 }
 
 // Plain path: one job, descriptor passed by value.
-template <int K, int NT>
+template <int K, int NT, int SYNC>
 __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
                                                   const int32_t *__restrict__ order) {
   __shared__ Smem<K> sm;
   const int alpha = ctrl->alpha;
-  load_job_tables<K>(jd, ctrl->gap, sm);
+  load_tables<K, NT>(jd, alpha, ctrl->gap, sm);
   const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   static_assert(NT == 64, "one wave per workgroup: the pop below is per wave");
@@ -314,7 +403,8 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
     const int got = atomicAdd(&ctrl->head, threadIdx.x == 0 ? 1 : 0);
     const int qi = __builtin_amdgcn_readfirstlane(got);
     if (qi >= jd.ntiles) break;
-    process_tile<K, NT>(jd, alpha, __builtin_amdgcn_readfirstlane(order[qi]), epoch, ctrl, sm);
+    process_tile<K, NT, SYNC>(jd, alpha, __builtin_amdgcn_readfirstlane(order[qi]), epoch,
+                              ctrl, sm);
   }
 }
 
@@ -470,21 +560,38 @@ __global__ void export_dirs_kernel(JobDev jd, uint8_t *out, int64_t ncell) {
 // ---------------------------------------------------------------------------
 constexpr int kFillThreads = 64;
 
+static int g_sync_mode = -1;
+
+static int sync_mode() {
+  if (g_sync_mode < 0) {
+    const char *e = getenv("MSA_SYNC");
+    g_sync_mode = (e && atoi(e) == 1) ? 1 : 2;
+  }
+  return g_sync_mode;
+}
+
 template <int K>
-static int launch_plain_k(const JobDev &jd, Ctrl *ctrl, const int32_t *order,
-                          int grid, hipStream_t s) {
-  hipLaunchKernelGGL((fill_kernel<K, kFillThreads>), dim3(grid), dim3(kFillThreads), 0, s,
-                     jd, ctrl, order);
-  if (hipGetLastError() != hipSuccess) return -1;
+static int launch_fill_k(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid,
+                         hipStream_t s) {
+  if (sync_mode() == 1)
+    hipLaunchKernelGGL((fill_kernel<K, kFillThreads, 1>), dim3(grid), dim3(kFillThreads), 0, s,
+                       jd, ctrl, order);
+  else
+    hipLaunchKernelGGL((fill_kernel<K, kFillThreads, 2>), dim3(grid), dim3(kFillThreads), 0, s,
+                       jd, ctrl, order);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int K>
+static int launch_traceback_k(const JobDev &jd, Ctrl *ctrl, hipStream_t s) {
   hipLaunchKernelGGL((traceback_kernel<K>), dim3(1), dim3(64), 0, s, jd, ctrl);
-  if (hipGetLastError() != hipSuccess) return -1;
-  return 0;
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int K>
 static int occupancy_k() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fill_kernel<K, kFillThreads>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fill_kernel<K, kFillThreads, 2>,
                                                    kFillThreads, 0) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
@@ -512,8 +619,12 @@ static int launch_export_k(const JobDev &jd, uint8_t *out, int64_t ncell, hipStr
     default: return -1;                            \
   }
 
-int launch_plain(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, hipStream_t s) {
-  MSA_DISPATCH_K(jd.k, launch_plain_k, jd, ctrl, order, grid, s);
+int launch_fill(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, hipStream_t s) {
+  MSA_DISPATCH_K(jd.k, launch_fill_k, jd, ctrl, order, grid, s);
+}
+
+int launch_traceback(const JobDev &jd, Ctrl *ctrl, hipStream_t s) {
+  MSA_DISPATCH_K(jd.k, launch_traceback_k, jd, ctrl, s);
 }
 
 int fill_occupancy(int k) { MSA_DISPATCH_K(k, occupancy_k); }

@@ -65,8 +65,15 @@ int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, 
   return ok ? MSA_OK : MSA_EDEVICE;
 }
 
+#ifdef MSA_TRACE
+// debug builds only: per-tile phase timestamps of the next fills
+static int64_t *g_trace_buf = nullptr;
+extern "C" void msa_dp_debug_set_trace(int64_t *d_buf) { g_trace_buf = d_buf; }
+#endif
+
 int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, uint8_t *d_aln,
-              int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s) {
+              int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,
+              int which) {
   JobDev jd;
   fill_jobdev(p, ws, 0, 0, &jd);  // alpha and gap are read from the control block
   jd.seqs = d_seqs;
@@ -75,12 +82,17 @@ int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, 
   jd.aln_cap = aln_cap;
   jd.aln_len_out = d_aln_len;
   jd.status_out = d_status;
+#ifdef MSA_TRACE
+  jd.trace = g_trace_buf;
+#endif
   int64_t grid = (int64_t)device_cu_count() * occupancy(p.k);
   if (grid > p.ntiles) grid = p.ntiles;
   if (grid < 1) grid = 1;
   Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
   const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
-  return launch_plain(jd, ctrl, order, (int)grid, s) == 0 ? MSA_OK : MSA_EDEVICE;
+  if ((which & 1) && launch_fill(jd, ctrl, order, (int)grid, s) != 0) return MSA_EDEVICE;
+  if ((which & 2) && launch_traceback(jd, ctrl, s) != 0) return MSA_EDEVICE;
+  return MSA_OK;
 }
 
 int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s) {

@@ -8,7 +8,8 @@
 namespace msa {
 
 // kernels (msa_kernels.hip)
-int launch_plain(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, hipStream_t s);
+int launch_fill(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, hipStream_t s);
+int launch_traceback(const JobDev &jd, Ctrl *ctrl, hipStream_t s);
 int launch_export(const JobDev &jd, uint8_t *out, int64_t ncell, hipStream_t s);
 int fill_occupancy(int k);
 
@@ -16,8 +17,10 @@ int fill_occupancy(int k);
 int device_cu_count();
 int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, int gap,
                       hipStream_t s);
+// which: 1 = fill only, 2 = traceback only, 3 = both
 int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, uint8_t *d_aln,
-              int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s);
+              int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,
+              int which = 3);
 int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s);
 
 }  // namespace msa
