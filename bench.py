@@ -95,6 +95,19 @@ def cpu_baseline():
                       f"{job.cells} cells) in {dt:.2f} s, single thread, gcc -O2"}
 
 
+def copy_probe(nbytes, steps):
+    """Plain device-to-device copy of a known size: the reference for scaling
+    the FETCH_SIZE / WRITE_SIZE hardware counters into HBM bytes."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "launches": steps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +115,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device copy of BYTES (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs each alignment on a "
@@ -112,6 +127,9 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if a.copy_probe:
+        copy_probe(a.copy_probe, a.steps)
+        return
     main_r = time_workload(MAIN, a.steps, a.warmup)
     extra = {}
     if not a.no_extra:

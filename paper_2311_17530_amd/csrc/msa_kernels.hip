@@ -44,6 +44,25 @@ struct Cfg {
   static constexpr int M = (1 << K) - 1;
   static constexpr int H = K * (T - 1) + 1;  // hyperplanes of a full tile
   static constexpr int DBS = (NC + 15) / 16 * 16;
+  static constexpr int hwidth(int h) {  // cells of a full tile on hyperplane h
+    int cnt[K * 32] = {};
+    cnt[0] = 1;
+    int top = 0;
+    for (int d = 0; d < K; ++d) {  // convolve with (1 + x + ... + x^{T-1})
+      int nxt[K * 32] = {};
+      for (int a = 0; a <= top; ++a)
+        for (int b = 0; b < T; ++b) nxt[a + b] += cnt[a];
+      top += T - 1;
+      for (int a = 0; a <= top; ++a) cnt[a] = nxt[a];
+    }
+    return h <= top ? cnt[h] : 0;
+  }
+  static constexpr int maxw() {
+    int m = 0;
+    for (int h = 0; h < H; ++h) m = hwidth(h) > m ? hwidth(h) : m;
+    return m;
+  }
+  static constexpr int MAXW = maxw();
   static constexpr int sstride(int i) {  // LDS strides: 1, RP, RP*E, RP*E^2, ...
     return i == K - 1 ? 1 : RP * ipow(E, K - 2 - i);
   }
@@ -58,6 +77,32 @@ struct Cfg {
     return o;
   }
 };
+
+
+// Hyperplane starts of a full tile (prefix sums of hwidth), a compile-time
+// table in constant memory: read with wave-uniform (scalar) loads, so no LDS
+// round trip precedes the per-hyperplane cell reads.
+template <int K>
+struct HsTab {
+  int32_t v[Cfg<K>::H + 2];
+};
+template <int K>
+constexpr HsTab<K> make_hs() {
+  HsTab<K> t{};
+  int acc = 0;
+  for (int h = 0; h < Cfg<K>::H; ++h) {
+    t.v[h] = acc;
+    acc += Cfg<K>::hwidth(h);
+  }
+  t.v[Cfg<K>::H] = acc;
+  t.v[Cfg<K>::H + 1] = acc;
+  return t;
+}
+template <int K>
+__constant__ HsTab<K> kHs = make_hs<K>();
+
+static_assert(make_hs<3>().v[Cfg<3>::H] == Cfg<3>::NC, "hyperplane widths sum to T^k");
+static_assert(make_hs<4>().v[Cfg<4>::H] == Cfg<4>::NC, "hyperplane widths sum to T^k");
 
 template <int K>
 struct Smem {
@@ -145,9 +190,11 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
   }
 
   // ---- wait for the k face predecessors (diagonal ones are implied) ----
-  // Lane i polls the flag of tile c - e_i.  The loop condition is a wave vote
-  // and every exit test is wave-uniform, so the wave never splits here.
-  {
+  // Wave 0 polls: lane i reads the flag of tile c - e_i.  The loop condition is
+  // a wave vote and every exit test is wave-uniform, so the wave never splits;
+  // the other waves wait at the barrier below.
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) >> 6;
+  if (wave == 0) {
     const int32_t *f = jd.flags;
     bool need = false;
 #pragma unroll
@@ -173,6 +220,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
       __builtin_amdgcn_s_sleep(1);
     }
   }
+  __syncthreads();
   if constexpr (SYNC != 2)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   else
@@ -180,21 +228,28 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
 
   MSA_TRACE_POINT(jd, tile, 1);
   // ---- residues of this tile (v = lo + q; sequence index v - 1) ----
+  // Loads are issued unconditionally from clamped in-range addresses (no
+  // per-lane branch around a load, so all of them are in flight together); the
+  // values are selected and checked afterwards.
+  {
+    int r[K];
+    const bool any_seq = jd.total_len > 0;  // uniform: no sequence bytes at all
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
-    if (tid < T) {
-      const int q = tid;
+    for (int i = 0; i < K; ++i) {
+      const int q = tid < T ? tid : 0;
       const int v = lo[i] + q;
-      int r = 0;
-      if (q < ext[i] && v >= 1) {
-        r = jd.seqs[jd.seq_off[i] + v - 1];
-        if (r >= alpha) {
-          atomicCAS(&ctrl->status, ST_OK, ST_EINVAL);
-          r = 0;
-        }
-      }
-      sm.RES[i * T + q] = (uint8_t)r;
+      const bool use = tid < T && q < ext[i] && v >= 1;
+      const int pos = use ? jd.seq_off[i] + v - 1 : 0;
+      r[i] = any_seq ? (int)jd.seqs[pos] : 0;
+      r[i] = use ? r[i] : 0;
     }
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      bad = bad || r[i] >= alpha;
+      if (tid < T) sm.RES[i * T + tid] = (uint8_t)(r[i] >= alpha ? 0 : r[i]);
+    }
+    if (bad) atomicCAS(&ctrl->status, ST_OK, ST_EINVAL);
   }
 
   // ---- halo: layer l_i = 0 along each dimension ----
@@ -235,7 +290,9 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
               foff += (int64_t)v * jd.fstride[i][j];
             }
             sidx[di][it] = valid ? s : -1;
-            val[di][it] = (valid && !neg) ? face_load<SYNC>(plane + foff) : kNegKey;
+            // unconditional load from a clamped in-range offset, then select
+            const int32_t got = face_load<SYNC>(plane + ((valid && !neg) ? foff : 0));
+            val[di][it] = (valid && !neg) ? got : kNegKey;
           }
         }
 #pragma unroll
@@ -282,16 +339,42 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
     int32_t gk[K + 1];
 #pragma unroll
     for (int cb = 0; cb <= K; ++cb) gk[cb] = sm.GK[cb];
+    // Thread t takes the cells t, t + NT, ... of each hyperplane (at most U of
+    // them); the packed coordinates of hyperplane h + 1 are read from LDS while
+    // hyperplane h is computed, so one LDS round trip per hyperplane remains on
+    // the dependency chain.
+    constexpr int U = (C::MAXW + NT - 1) / NT;
+    constexpr uint32_t kNone = 0xFFFFu;
+    constexpr bool POW2 = (1 << C::B) == T;
+    uint32_t cur[U], nxt[U];
+    {
+      const int b0 = kHs<K>.v[0];
+      const int e0 = kHs<K>.v[1];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = b0 + tid + u * NT;
+        cur[u] = e < e0 ? (uint32_t)sm.CELLS[e] : kNone;
+      }
+    }
     for (int h = 0; h <= hmax; ++h) {
-      const int beg = __builtin_amdgcn_readfirstlane(sm.HS[h]);
-      const int end = __builtin_amdgcn_readfirstlane(sm.HS[h + 1]);
-      for (int e = beg + tid; e < end; e += NT) {
-        const uint32_t pk = sm.CELLS[e];
+      {
+        const int b1 = kHs<K>.v[h + 1];
+        const int e1 = kHs<K>.v[h + 2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = b1 + tid + u * NT;
+          nxt[u] = e < e1 ? (uint32_t)sm.CELLS[e] : kNone;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t pk = cur[u];
+        if (pk == kNone) continue;
         int q[K];
         bool ok = true;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-          q[i] = (pk >> (i * C::B)) & ((1u << C::B) - 1);
+          q[i] = (pk >> ((K - 1 - i) * C::B)) & ((1u << C::B) - 1);
           ok = ok && (full || q[i] < ext[i]);
         }
         if (!ok) continue;
@@ -301,12 +384,18 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
           sidx += (q[i] + 1) * C::sstride(i);
           didx += q[i] * C::dstride(i);
         }
+        if constexpr (POW2) didx = (int)pk;  // packed coordinates == block index
         int32_t pv[C::NP > 0 ? C::NP : 1];
 #pragma unroll
         for (int i = 0; i < K; ++i)
 #pragma unroll
-          for (int j = i + 1; j < K; ++j)
-            pv[C::pair_index(i, j)] = sm.PT[C::pair_index(i, j) * T * T + q[i] * T + q[j]];
+          for (int j = i + 1; j < K; ++j) {
+            // adjacent dimensions: q_i * T + q_j is a bit field of pk
+            const int pidx = (POW2 && j == i + 1)
+                                 ? (int)((pk >> ((K - 1 - j) * C::B)) & ((1u << (2 * C::B)) - 1))
+                                 : q[i] * T + q[j];
+            pv[C::pair_index(i, j)] = sm.PT[C::pair_index(i, j) * T * T + pidx];
+          }
         int32_t best = INT32_MIN;
 #pragma unroll
         for (int b = 1; b <= M; ++b) {
@@ -324,6 +413,8 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
         sm.DIRB[didx] = (uint8_t)best;
       }
       __syncthreads();
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
     }
   }
   __syncthreads();
@@ -337,26 +428,46 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
   }
 
   // ---- export upper faces (layer l_i = ext_i) for the successor along i ----
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    if (c[i] >= jd.P[i] - 1) continue;
+  // All LDS reads of a pass first (unconditional, clamped index), then the
+  // predicated global stores, so the reads are not serialised against them.
+  {
     constexpr int cnt = ipow(T, K - 1);
-    int32_t *plane = jd.faces + jd.face_off[i] + (int64_t)c[i] * jd.fplane[i];
-    for (int idx = tid; idx < cnt; idx += NT) {
-      int rem = idx;
-      int sidx = ext[i] * C::sstride(i);
-      bool valid = true;
-      int64_t foff = 0;
+    constexpr int IT = (cnt + NT - 1) / NT;
+    constexpr int DG = K * IT <= 32 ? K : 1;  // dimensions per pass
+    for (int i0 = 0; i0 < K; i0 += DG) {
+      int32_t val[DG][IT];
+      int64_t fo[DG][IT];
+      bool st[DG][IT];
 #pragma unroll
-      for (int j = K - 1; j >= 0; --j) {
-        if (j == i) continue;
-        const int qq = rem % T;
-        rem /= T;
-        valid = valid && qq < ext[j];
-        sidx += (qq + 1) * C::sstride(j);
-        foff += (int64_t)(lo[j] + qq) * jd.fstride[i][j];
+      for (int di = 0; di < DG; ++di) {
+        const int i = i0 + di;
+        const bool has_succ = c[i] < jd.P[i] - 1;
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+          const int idx = tid + it * NT;
+          int rem = idx;
+          int sidx = ext[i] * C::sstride(i);
+          bool valid = has_succ && idx < cnt;
+          int64_t foff = 0;
+#pragma unroll
+          for (int j = K - 1; j >= 0; --j) {
+            if (j == i) continue;
+            const int qq = rem % T;
+            rem /= T;
+            valid = valid && qq < ext[j];
+            sidx += (qq + 1) * C::sstride(j);
+            foff += (int64_t)(lo[j] + qq) * jd.fstride[i][j];
+          }
+          val[di][it] = sm.S[valid ? sidx : 0];
+          fo[di][it] = jd.face_off[i] + (int64_t)c[i] * jd.fplane[i] + foff;
+          st[di][it] = valid;
+        }
       }
-      if (valid) face_store<SYNC>(plane + foff, sm.S[sidx]);
+#pragma unroll
+      for (int di = 0; di < DG; ++di)
+#pragma unroll
+        for (int it = 0; it < IT; ++it)
+          if (st[di][it]) face_store<SYNC>(jd.faces + fo[di][it], val[di][it]);
     }
   }
 
@@ -369,8 +480,10 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
 
   MSA_TRACE_POINT(jd, tile, 5);
   // ---- publish completion ----
-  // Every lane stores the same flag value: a lane-divergent branch next to the
-  // persistent loop's back edge lets the compiler peel lane 0 off the loop.
+  // Each wave makes its own stores visible, the barrier orders all waves before
+  // wave 0 stores the flag.  All 64 lanes of wave 0 store the same value: a
+  // lane-divergent branch next to the persistent loop's back edge lets the
+  // compiler peel lanes off the loop.
   if constexpr (SYNC == 1) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   } else {
@@ -379,7 +492,8 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }
   __syncthreads();
-  __hip_atomic_store(jd.flags + tile, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (wave == 0)
+    __hip_atomic_store(jd.flags + tile, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   MSA_TRACE_POINT(jd, tile, 6);
 #ifdef MSA_TRACE
   if (jd.trace) jd.trace[(int64_t)tile * 8 + 7] = blockIdx.x;
@@ -395,13 +509,20 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
   load_tables<K, NT>(jd, alpha, ctrl->gap, sm);
   const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  static_assert(NT == 64, "one wave per workgroup: the pop below is per wave");
+  static_assert(NT % 64 == 0, "whole waves per workgroup");
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) >> 6;
+  __shared__ int32_t bcast;
   for (;;) {
-    // Queue pop without a lane-divergent branch: every lane issues the atomic,
-    // only lane 0 adds 1, and lane 0's result is broadcast as a wave-uniform
-    // (SGPR) value, so the loop exit below is uniform.
-    const int got = atomicAdd(&ctrl->head, threadIdx.x == 0 ? 1 : 0);
-    const int qi = __builtin_amdgcn_readfirstlane(got);
+    // Queue pop without a lane-divergent branch: wave 0's lanes all issue the
+    // atomic, only lane 0 adds 1, lane 0's result is broadcast through LDS and
+    // read back as a wave-uniform (SGPR) value, so the loop exit is uniform.
+    if (wave == 0) {
+      const int got = atomicAdd(&ctrl->head, threadIdx.x == 0 ? 1 : 0);
+      bcast = __builtin_amdgcn_readfirstlane(got);
+    }
+    __syncthreads();
+    const int qi = __builtin_amdgcn_readfirstlane(bcast);
+    __syncthreads();
     if (qi >= jd.ntiles) break;
     process_tile<K, NT, SYNC>(jd, alpha, __builtin_amdgcn_readfirstlane(order[qi]), epoch,
                               ctrl, sm);
@@ -558,7 +679,7 @@ __global__ void export_dirs_kernel(JobDev jd, uint8_t *out, int64_t ncell) {
 // ---------------------------------------------------------------------------
 // Host-side launchers (called from the ABI layer).
 // ---------------------------------------------------------------------------
-constexpr int kFillThreads = 64;
+constexpr int kFillThreads = 256;  // four waves per tile
 
 static int g_sync_mode = -1;
 

@@ -70,7 +70,8 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
   q.off_path = o;   o = align256(o + std::max<int64_t>(q.total_len, 1));
   q.off_faces = o;
   if (!mul_ok(q.face_elems, 4, lim)) return MSA_ENOMEM;
-  o = align256(o + q.face_elems * 4);
+  // at least one block, so a clamped (unconditional) read at offset 0 is in range
+  o = align256(o + std::max<int64_t>(q.face_elems * 4, 256));
   q.off_dir = o;
   if (!mul_ok(q.ntiles, q.dbs, lim)) return MSA_ENOMEM;
   o = align256(o + q.ntiles * q.dbs);
@@ -105,7 +106,7 @@ void make_cell_table(int k, int T, std::vector<uint32_t> *cells, std::vector<int
     for (int i = k - 1; i >= 0; --i) {
       const int q = (int)(rem % T);
       rem /= T;
-      pk |= (uint32_t)q << (i * B);
+      pk |= (uint32_t)q << ((k - 1 - i) * B);  // last dimension in the low bits
       s += q;
     }
     (*cells)[fillpos[s]++] = pk;
