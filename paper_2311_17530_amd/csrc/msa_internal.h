@@ -50,6 +50,11 @@ struct JobDev {
   int64_t *aln_len_out;
   int32_t *status_out;
   int64_t *trace;             // optional per-tile phase timestamps (debug builds)
+  // batched path only
+  int32_t *jstatus;           // per-job status (bad residue code)
+  const int32_t *wcnt;        // (k+1) x nwaves: tuples (c_d..c_{k-1}) summing to s
+  const int32_t *wstart;      // nwaves + 1: tiles in the waves before w
+  int64_t qbase;              // first queue slot of this job
 };
 
 // Control block of one persistent launch (in device memory).

@@ -111,7 +111,6 @@ struct Smem {
   int32_t SUB[kSubLds * kSubLds];                 // substitution matrix << k
   uint16_t CELLS[Cfg<K>::NC];                     // hyperplane-sorted cells
   int32_t HS[Cfg<K>::H + 1];                      // hyperplane starts
-  int32_t GK[K + 1];                              // gap term per |b|, << k
   uint8_t RES[K * Cfg<K>::T];                     // residues of the tile
   alignas(16) uint8_t DIRB[Cfg<K>::DBS];          // direction bytes
 };
@@ -154,12 +153,11 @@ __device__ inline void face_store(int32_t *p, int32_t v) {
 
 // Per-launch constant tables into LDS (done once per persistent workgroup).
 template <int K, int NT>
-__device__ void load_tables(const JobDev &jd, int alpha, int gap, Smem<K> &sm) {
+__device__ void load_tables(const JobDev &jd, int alpha, Smem<K> &sm) {
   using C = Cfg<K>;
   const int tid = threadIdx.x;
   for (int h = tid; h <= C::H; h += NT) sm.HS[h] = jd.hstart[h];
   for (int e = tid; e < C::NC; e += NT) sm.CELLS[e] = (uint16_t)jd.cells[e];
-  if (tid <= K) sm.GK[tid] = (gap * tid * (K - tid)) * (1 << K);
   if (alpha <= kSubLds)
     for (int e = tid; e < alpha * alpha; e += NT)
       sm.SUB[(e / alpha) * kSubLds + e % alpha] = ((int32_t)jd.sub[e]) * (1 << K);
@@ -169,8 +167,8 @@ __device__ void load_tables(const JobDev &jd, int alpha, int gap, Smem<K> &sm) {
 // One tile of the fill.
 // ---------------------------------------------------------------------------
 template <int K, int NT, int SYNC>
-__device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
-                             Ctrl *ctrl, Smem<K> &sm) {
+__device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int epoch,
+                             Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int E = C::E;
@@ -249,7 +247,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
       bad = bad || r[i] >= alpha;
       if (tid < T) sm.RES[i * T + tid] = (uint8_t)(r[i] >= alpha ? 0 : r[i]);
     }
-    if (bad) atomicCAS(&ctrl->status, ST_OK, ST_EINVAL);
+    if (bad) atomicCAS(jstatus, ST_OK, ST_EINVAL);
   }
 
   // ---- halo: layer l_i = 0 along each dimension ----
@@ -338,7 +336,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int tile, int epoch,
     for (int i = 0; i < K; ++i) hmax += ext[i] - 1;
     int32_t gk[K + 1];
 #pragma unroll
-    for (int cb = 0; cb <= K; ++cb) gk[cb] = sm.GK[cb];
+    for (int cb = 0; cb <= K; ++cb) gk[cb] = (gap * cb * (K - cb)) * (1 << K);
     // Thread t takes the cells t, t + NT, ... of each hyperplane (at most U of
     // them); the packed coordinates of hyperplane h + 1 are read from LDS while
     // hyperplane h is computed, so one LDS round trip per hyperplane remains on
@@ -506,7 +504,8 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
                                                   const int32_t *__restrict__ order) {
   __shared__ Smem<K> sm;
   const int alpha = ctrl->alpha;
-  load_tables<K, NT>(jd, alpha, ctrl->gap, sm);
+  const int gap = ctrl->gap;
+  load_tables<K, NT>(jd, alpha, sm);
   const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   static_assert(NT % 64 == 0, "whole waves per workgroup");
@@ -524,8 +523,8 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
     const int qi = __builtin_amdgcn_readfirstlane(bcast);
     __syncthreads();
     if (qi >= jd.ntiles) break;
-    process_tile<K, NT, SYNC>(jd, alpha, __builtin_amdgcn_readfirstlane(order[qi]), epoch,
-                              ctrl, sm);
+    process_tile<K, NT, SYNC>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]), epoch,
+                              ctrl, &ctrl->status, sm);
   }
 }
 
@@ -533,15 +532,13 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
 // Traceback: one workgroup of one wave.
 // ---------------------------------------------------------------------------
 template <int K>
-__device__ void traceback_job(const JobDev &jd, Ctrl *ctrl, uint8_t *dirb,
-                              int32_t *bc) {
+__device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int M = C::M;
   const int tid = threadIdx.x;
   const int NT = blockDim.x;
-  int status = __builtin_amdgcn_readfirstlane(
-      __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  int status = __builtin_amdgcn_readfirstlane(status_in);
   int v[K];
   bool done = true;
 #pragma unroll
@@ -632,14 +629,13 @@ __device__ void traceback_job(const JobDev &jd, Ctrl *ctrl, uint8_t *dirb,
     *jd.status_out = status;
     if (status != ST_OK) *jd.score_out = 0;
   }
-  (void)bc;
 }
 
 template <int K>
 __global__ __launch_bounds__(64) void traceback_kernel(JobDev jd, Ctrl *ctrl) {
   __shared__ alignas(16) uint8_t dirb[Cfg<K>::DBS];
-  __shared__ int32_t bc;
-  traceback_job<K>(jd, ctrl, dirb, &bc);
+  traceback_job<K>(jd, __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                   dirb);
   __syncthreads();
   if (threadIdx.x == 0) {
     // ready the control block for the next launch on this workspace
@@ -673,6 +669,152 @@ __global__ void export_dirs_kernel(JobDev jd, uint8_t *out, int64_t ncell) {
     }
     const int byte = jd.dir[(int64_t)t * C::DBS + d];
     out[lin] = (uint8_t)(C::M - (byte & C::M));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched path: many jobs (uneven k and lengths) in one persistent launch.
+// ---------------------------------------------------------------------------
+
+// Queue construction: slot of tile t of job j = qbase + (tiles of the waves
+// before t's wave) + (rank of t among its wave's tiles in lexicographic
+// order).  Every job's tiles therefore appear in wave order, which makes the
+// concatenated queue a topological order of all dependencies.
+__global__ void batch_queue_kernel(const JobDev *__restrict__ jobs, int njobs,
+                                   const int64_t *__restrict__ jtiles, int32_t *qjob,
+                                   int32_t *qtile) {
+  const int64_t total = jtiles[njobs];
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = njobs;  // jtiles[lo] <= g < jtiles[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (jtiles[mid] <= g) lo = mid; else hi = mid;
+    }
+    const JobDev &jd = jobs[lo];
+    const int t = (int)(g - jtiles[lo]);
+    int c[kMaxK];
+    int w = 0;
+    for (int d = 0; d < jd.k; ++d) {
+      c[d] = (t / jd.tstride[d]) % jd.P[d];
+      w += c[d];
+    }
+    int64_t rank = 0;
+    int s = w;
+    for (int d = 0; d < jd.k - 1; ++d) {
+      for (int cc = 0; cc < c[d]; ++cc)
+        if (s - cc >= 0) rank += jd.wcnt[(d + 1) * jd.nwaves + (s - cc)];
+      s -= c[d];
+    }
+    const int64_t pos = jd.qbase + jd.wstart[w] + rank;
+    qjob[pos] = lo;
+    qtile[pos] = t;
+  }
+}
+
+template <int K>
+constexpr size_t smem_bytes() { return sizeof(Smem<K>); }
+template <int KLO, int KHI>
+constexpr size_t batch_smem_bytes() {
+  size_t m = 0;
+  for (int k = KLO; k <= KHI; ++k) {
+    const size_t b = k == 2 ? smem_bytes<2>() : k == 3 ? smem_bytes<3>() : k == 4 ? smem_bytes<4>()
+                   : k == 5 ? smem_bytes<5>() : k == 6 ? smem_bytes<6>() : k == 7 ? smem_bytes<7>()
+                   : smem_bytes<8>();
+    m = b > m ? b : m;
+  }
+  return m;
+}
+
+// One tile of job `jd` with K = k; reloads the per-k cell table and the
+// job's substitution matrix into LDS when they differ from the cached ones.
+template <int K, int NT>
+__device__ void batch_tile(const JobDev &jd, int tile, int epoch, Ctrl *ctrl, void *smraw,
+                           int &cur_k, const int8_t *&cur_sub) {
+  Smem<K> &sm = *reinterpret_cast<Smem<K> *>(smraw);
+  if (cur_k != K || cur_sub != jd.sub) {
+    __syncthreads();
+    load_tables<K, NT>(jd, jd.alpha, sm);
+    __syncthreads();
+    cur_k = K;
+    cur_sub = jd.sub;
+  }
+  process_tile<K, NT, 2>(jd, jd.alpha, jd.gap, tile, epoch, ctrl, jd.jstatus, sm);
+}
+
+template <int KLO, int KHI, int NT>
+__global__ __launch_bounds__(NT) void batch_fill_kernel(const JobDev *__restrict__ jobs,
+                                                        const int32_t *__restrict__ qjob,
+                                                        const int32_t *__restrict__ qtile,
+                                                        int32_t total, Ctrl *ctrl) {
+  __shared__ alignas(16) char smraw[batch_smem_bytes<KLO, KHI>()];
+  __shared__ int32_t bcast;
+  const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) >> 6;
+  int cur_k = -1;
+  const int8_t *cur_sub = nullptr;
+  for (;;) {
+    if (wave == 0) {  // see fill_kernel: no lane-divergent branch around the pop
+      const int got = atomicAdd(&ctrl->head, threadIdx.x == 0 ? 1 : 0);
+      bcast = __builtin_amdgcn_readfirstlane(got);
+    }
+    __syncthreads();
+    const int q = __builtin_amdgcn_readfirstlane(bcast);
+    __syncthreads();
+    if (q >= total) break;
+    const int j = __builtin_amdgcn_readfirstlane(qjob[q]);
+    const int tile = __builtin_amdgcn_readfirstlane(qtile[q]);
+    const JobDev &jd = jobs[j];
+    switch (jd.k) {
+      case 2: if constexpr (KLO <= 2 && 2 <= KHI) batch_tile<2, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 3: if constexpr (KLO <= 3 && 3 <= KHI) batch_tile<3, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 4: if constexpr (KLO <= 4 && 4 <= KHI) batch_tile<4, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 5: if constexpr (KLO <= 5 && 5 <= KHI) batch_tile<5, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 6: if constexpr (KLO <= 6 && 6 <= KHI) batch_tile<6, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 7: if constexpr (KLO <= 7 && 7 <= KHI) batch_tile<7, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 8: if constexpr (KLO <= 8 && 8 <= KHI) batch_tile<8, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      default: break;
+    }
+  }
+}
+
+// One workgroup (one wave) per job: walk, expand, write the outputs.
+template <int KLO, int KHI>
+__global__ __launch_bounds__(64) void batch_traceback_kernel(const JobDev *__restrict__ jobs,
+                                                             int njobs, Ctrl *ctrl) {
+  __shared__ alignas(16) uint8_t dirb[4096];
+  const int j = blockIdx.x;
+  if (j >= njobs) return;
+  const JobDev &jd = jobs[j];
+  const int gst = __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int jst = __hip_atomic_load(jd.jstatus, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int st = gst != ST_OK ? gst : jst;
+  switch (jd.k) {
+    case 2: if constexpr (KLO <= 2 && 2 <= KHI) traceback_job<2>(jd, st, dirb); break;
+    case 3: if constexpr (KLO <= 3 && 3 <= KHI) traceback_job<3>(jd, st, dirb); break;
+    case 4: if constexpr (KLO <= 4 && 4 <= KHI) traceback_job<4>(jd, st, dirb); break;
+    case 5: if constexpr (KLO <= 5 && 5 <= KHI) traceback_job<5>(jd, st, dirb); break;
+    case 6: if constexpr (KLO <= 6 && 6 <= KHI) traceback_job<6>(jd, st, dirb); break;
+    case 7: if constexpr (KLO <= 7 && 7 <= KHI) traceback_job<7>(jd, st, dirb); break;
+    case 8: if constexpr (KLO <= 8 && 8 <= KHI) traceback_job<8>(jd, st, dirb); break;
+    default: break;
+  }
+}
+
+// Clears the completion flags of a launch (a kernel, not a memset, so that the
+// launch sequence can be captured in a graph).
+__global__ void batch_zero_kernel(int32_t *flags, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    flags[i] = 0;
+}
+
+// Readies the control block for the next launch on the same arena.
+__global__ void batch_finish_kernel(Ctrl *ctrl) {
+  if (threadIdx.x == 0) {
+    ctrl->head = 0;
+    ctrl->status = ST_OK;
+    ctrl->epoch = ctrl->epoch + 1;
   }
 }
 
@@ -752,6 +894,52 @@ int fill_occupancy(int k) { MSA_DISPATCH_K(k, occupancy_k); }
 
 int launch_export(const JobDev &jd, uint8_t *out, int64_t ncell, hipStream_t s) {
   MSA_DISPATCH_K(jd.k, launch_export_k, jd, out, ncell, s);
+}
+
+}  // namespace msa
+
+// ---------------------------------------------------------------------------
+// Batched launches: k class 0 covers k = 2..4, class 1 covers k = 5..8.
+// ---------------------------------------------------------------------------
+namespace msa {
+
+constexpr int kBatchThreads = 256;
+
+template <int KLO, int KHI>
+static int launch_batch_k(const JobDev *d_jobs, int njobs, const int64_t *d_jtiles,
+                          int32_t *qjob, int32_t *qtile, int64_t total, int32_t *flags,
+                          Ctrl *ctrl, int grid, hipStream_t s) {
+  int64_t qb = (total + 255) / 256;
+  if (qb > 8192) qb = 8192;
+  if (qb < 1) qb = 1;
+  hipLaunchKernelGGL(batch_zero_kernel, dim3((unsigned)qb), dim3(256), 0, s, flags, total);
+  hipLaunchKernelGGL(batch_queue_kernel, dim3((unsigned)qb), dim3(256), 0, s, d_jobs, njobs,
+                     d_jtiles, qjob, qtile);
+  hipLaunchKernelGGL((batch_fill_kernel<KLO, KHI, kBatchThreads>), dim3(grid),
+                     dim3(kBatchThreads), 0, s, d_jobs, qjob, qtile, (int32_t)total, ctrl);
+  hipLaunchKernelGGL((batch_traceback_kernel<KLO, KHI>), dim3(njobs), dim3(64), 0, s, d_jobs,
+                     njobs, ctrl);
+  hipLaunchKernelGGL(batch_finish_kernel, dim3(1), dim3(64), 0, s, ctrl);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_jtiles,
+                 int32_t *qjob, int32_t *qtile, int64_t total, int32_t *flags, Ctrl *ctrl,
+                 int grid, hipStream_t s) {
+  if (kclass == 0)
+    return launch_batch_k<2, 4>(d_jobs, njobs, d_jtiles, qjob, qtile, total, flags, ctrl, grid, s);
+  return launch_batch_k<5, 8>(d_jobs, njobs, d_jtiles, qjob, qtile, total, flags, ctrl, grid, s);
+}
+
+int batch_occupancy(int kclass) {
+  int nb = 0;
+  hipError_t e = kclass == 0
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &nb, batch_fill_kernel<2, 4, kBatchThreads>, kBatchThreads, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &nb, batch_fill_kernel<5, 8, kBatchThreads>, kBatchThreads, 0);
+  if (e != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
 }
 
 }  // namespace msa

@@ -1,0 +1,346 @@
+// msa_launch.cpp -- staging and running one batched persistent launch.
+#include "msa_launch.h"
+
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+
+#include "msa_runtime.h"
+
+namespace msa {
+
+static int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+int validate_job(const msa_job &j, int64_t) {
+  if (j.k < 2 || j.k > MSA_MAX_K) return MSA_EINVAL;
+  if (!j.submat || j.alpha < 1 || j.alpha > 255) return MSA_EINVAL;
+  for (int i = 0; i < j.k; ++i) {
+    if (j.lens[i] < 0) return MSA_EINVAL;
+    if (j.lens[i] > 0 && !j.seqs[i]) return MSA_EINVAL;
+    for (int32_t t = 0; t < j.lens[i]; ++t)
+      if (j.seqs[i][t] >= j.alpha) return MSA_EINVAL;
+  }
+  Plan p;
+  int rc = make_plan(j.lens, j.k, &p);
+  if (rc) return rc;
+  return check_scoring(j.lens, j.k, j.submat, j.alpha, j.gap);
+}
+
+namespace {
+struct JobSizes {
+  Plan p;
+  int64_t cap = 0;       // alignment row capacity
+  int64_t nw = 0;        // waves
+  int64_t small = 0;     // host-initialised bytes
+  int64_t big = 0;       // device-only bytes (path, faces, dir)
+  int64_t out = 0;       // output rows
+};
+
+int sizes_of(const msa_job &j, JobSizes *s) {
+  int rc = make_plan(j.lens, j.k, &s->p);
+  if (rc) return rc;
+  const Plan &p = s->p;
+  s->cap = std::max<int64_t>(1, p.total_len);
+  s->nw = p.nwaves;
+  s->small = a256(std::max<int64_t>(p.total_len, 1)) +        // sequences
+             a256((int64_t)(j.k + 1) * p.nwaves * 4) +        // wave counts
+             a256((int64_t)(p.nwaves + 1) * 4) +              // wave starts
+             256;                                             // job status
+  s->big = a256(std::max<int64_t>(p.total_len, 1)) +          // traceback path
+           a256(std::max<int64_t>(p.face_elems * 4, 256)) +   // face planes
+           a256(p.ntiles * p.dbs);                            // direction blocks
+  s->out = a256((int64_t)j.k * s->cap);
+  return MSA_OK;
+}
+}  // namespace
+
+int64_t job_arena_bytes(const msa_job &j) {
+  JobSizes s;
+  if (sizes_of(j, &s)) return -1;
+  return s.small + s.big + s.out + 12 * s.p.ntiles + (int64_t)sizeof(JobDev) + 64;
+}
+
+int64_t Launch::overhead_bytes(int njobs, int64_t ntiles_total) {
+  int64_t tables = 0;
+  for (int k = 2; k <= kMaxK; ++k) {
+    const int T = tile_edge_for_k(k);
+    tables += a256((int64_t)ipow(T, k) * 4) + a256((int64_t)(k * (T - 1) + 2) * 4);
+  }
+  return 256 + tables + a256((int64_t)njobs * sizeof(JobDev)) + a256((int64_t)(njobs + 1) * 8) +
+         a256((int64_t)njobs * 24) + 3 * a256(ntiles_total * 4) + 255 * 255 * 4 + 4096;
+}
+
+Launch::~Launch() {
+  if (busy_) wait();
+  if (d_) (void)hipFree(d_);
+  if (h_in_) (void)hipHostFree(h_in_);
+  if (h_out_) (void)hipHostFree(h_out_);
+  if (done_) (void)hipEventDestroy(done_);
+  if (stream_) (void)hipStreamDestroy(stream_);
+}
+
+int Launch::init(int64_t bytes) {
+  if (hipGetDevice(&device_) != hipSuccess) return MSA_EDEVICE;
+  if (!stream_ && hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking) != hipSuccess)
+    return MSA_EDEVICE;
+  if (!done_ && hipEventCreateWithFlags(&done_, hipEventDisableTiming) != hipSuccess)
+    return MSA_EDEVICE;
+  if (cap_ < bytes) {
+    if (d_) (void)hipFree(d_);
+    d_ = nullptr;
+    cap_ = 0;
+    if (hipMalloc(&d_, bytes) != hipSuccess) {
+      d_ = nullptr;
+      return MSA_ENOMEM;
+    }
+    cap_ = bytes;
+  }
+  return MSA_OK;
+}
+
+int Launch::ensure_host(int64_t in_bytes, int64_t out_bytes) {
+  if (h_in_cap_ < in_bytes) {
+    if (h_in_) (void)hipHostFree(h_in_);
+    h_in_ = nullptr;
+    h_in_cap_ = 0;
+    const int64_t want = std::max<int64_t>(in_bytes, 1 << 20);
+    if (hipHostMalloc((void **)&h_in_, want, hipHostMallocDefault) != hipSuccess) return MSA_ENOMEM;
+    h_in_cap_ = want;
+  }
+  if (h_out_cap_ < out_bytes) {
+    if (h_out_) (void)hipHostFree(h_out_);
+    h_out_ = nullptr;
+    h_out_cap_ = 0;
+    const int64_t want = std::max<int64_t>(out_bytes, 1 << 20);
+    if (hipHostMalloc((void **)&h_out_, want, hipHostMallocDefault) != hipSuccess)
+      return MSA_ENOMEM;
+    h_out_cap_ = want;
+  }
+  return MSA_OK;
+}
+
+int Launch::start(const std::vector<const msa_job *> &jobs) {
+  if (busy_ || jobs.empty()) return MSA_EINVAL;
+  const int nj = (int)jobs.size();
+  const int kc = kclass_of(jobs[0]->k);
+  std::vector<JobSizes> sz(nj);
+  int64_t tiles = 0, small = 0, big = 0, outb = 0;
+  for (int i = 0; i < nj; ++i) {
+    if (kclass_of(jobs[i]->k) != kc) return MSA_EINVAL;
+    if (sizes_of(*jobs[i], &sz[i])) return MSA_EINVAL;
+    tiles += sz[i].p.ntiles;
+    small += sz[i].small;
+    big += sz[i].big;
+    outb += sz[i].out;
+  }
+  if (tiles >= ((int64_t)1 << 31) - 1) return MSA_ENOMEM;
+
+  // ---- layout: [inputs (one host-to-device copy)][outputs][device only] ----
+  int64_t o = 0;
+  const int64_t off_ctrl = o;  o += 256;
+  int64_t off_cells[kMaxK + 1] = {}, off_hs[kMaxK + 1] = {};
+  bool need_k[kMaxK + 1] = {};
+  for (int i = 0; i < nj; ++i) need_k[jobs[i]->k] = true;
+  std::vector<std::vector<uint32_t>> cells(kMaxK + 1);
+  std::vector<std::vector<int32_t>> hs(kMaxK + 1);
+  for (int k = 2; k <= kMaxK; ++k) {
+    if (!need_k[k]) continue;
+    make_cell_table(k, tile_edge_for_k(k), &cells[k], &hs[k]);
+    off_cells[k] = o; o = a256(o + (int64_t)cells[k].size() * 4);
+    off_hs[k] = o;    o = a256(o + (int64_t)hs[k].size() * 4);
+  }
+  const int64_t off_jobs = o;  o = a256(o + (int64_t)nj * sizeof(JobDev));
+  const int64_t off_jt = o;    o = a256(o + (int64_t)(nj + 1) * 8);
+  // substitution matrices, deduplicated by content
+  std::map<std::string, int64_t> subs;
+  std::vector<int64_t> sub_off(nj);
+  for (int i = 0; i < nj; ++i) {
+    const msa_job &j = *jobs[i];
+    std::string key((const char *)j.submat, (size_t)j.alpha * j.alpha);
+    key.push_back((char)j.alpha);
+    auto it = subs.find(key);
+    if (it == subs.end()) {
+      it = subs.emplace(key, o).first;
+      o = a256(o + (int64_t)j.alpha * j.alpha);
+    }
+    sub_off[i] = it->second;
+  }
+  std::vector<int64_t> job_small(nj);
+  for (int i = 0; i < nj; ++i) {
+    job_small[i] = o;
+    o += sz[i].small;
+  }
+  const int64_t in_bytes = o;
+  // outputs
+  const int64_t off_out = o;
+  const int64_t off_score = o;  o = a256(o + (int64_t)nj * 8);
+  const int64_t off_len = o;    o = a256(o + (int64_t)nj * 8);
+  const int64_t off_stat = o;   o = a256(o + (int64_t)nj * 4);
+  std::vector<int64_t> job_out(nj);
+  for (int i = 0; i < nj; ++i) {
+    job_out[i] = o;
+    o += sz[i].out;
+  }
+  const int64_t out_bytes = o - off_out;
+  // device only
+  const int64_t off_qjob = o;  o = a256(o + tiles * 4);
+  const int64_t off_qtile = o; o = a256(o + tiles * 4);
+  const int64_t off_flags = o; o = a256(o + tiles * 4);
+  std::vector<int64_t> job_big(nj);
+  for (int i = 0; i < nj; ++i) {
+    job_big[i] = o;
+    o += sz[i].big;
+  }
+  if (o > cap_) return MSA_ENOMEM;
+  int rc = ensure_host(in_bytes, out_bytes);
+  if (rc) return rc;
+
+  // ---- host image of the input region ----
+  char *h = h_in_;
+  memset(h, 0, (size_t)in_bytes);
+  Ctrl ctrl;
+  memset(&ctrl, 0, sizeof(ctrl));
+  ctrl.epoch = 1;
+  memcpy(h + off_ctrl, &ctrl, sizeof(ctrl));
+  for (int k = 2; k <= kMaxK; ++k) {
+    if (!need_k[k]) continue;
+    memcpy(h + off_cells[k], cells[k].data(), cells[k].size() * 4);
+    memcpy(h + off_hs[k], hs[k].data(), hs[k].size() * 4);
+  }
+  for (auto &kv : subs)
+    memcpy(h + kv.second, kv.first.data(), kv.first.size() - 1);
+  int64_t *jt = reinterpret_cast<int64_t *>(h + off_jt);
+  jt[0] = 0;
+  meta_.assign(nj, Meta());
+  JobDev *jd_all = reinterpret_cast<JobDev *>(h + off_jobs);
+  for (int i = 0; i < nj; ++i) {
+    const msa_job &j = *jobs[i];
+    const Plan &p = sz[i].p;
+    jt[i + 1] = jt[i] + p.ntiles;
+    JobDev jd;
+    fill_jobdev(p, nullptr, j.alpha, j.gap, &jd);
+    // small region of this job
+    int64_t so = job_small[i];
+    char *hs_base = h + so;
+    int64_t pos = 0;
+    for (int d = 0; d < j.k; ++d) {
+      if (j.lens[d] > 0) memcpy(hs_base + pos, j.seqs[d], (size_t)j.lens[d]);
+      pos += j.lens[d];
+    }
+    const int64_t o_seq = so;
+    so += a256(std::max<int64_t>(p.total_len, 1));
+    const int64_t o_wcnt = so;
+    int32_t *wc = reinterpret_cast<int32_t *>(h + so);
+    const int nw = p.nwaves;
+    // wc[d][s]: coordinate tuples (c_d..c_{k-1}) with sum s
+    for (int s = 0; s < nw; ++s) wc[j.k * nw + s] = (s == 0);
+    for (int d = j.k - 1; d >= 0; --d)
+      for (int s = 0; s < nw; ++s) {
+        int64_t acc = 0;
+        for (int c = 0; c < p.P[d] && c <= s; ++c) acc += wc[(d + 1) * nw + (s - c)];
+        wc[d * nw + s] = (int32_t)acc;
+      }
+    so += a256((int64_t)(j.k + 1) * nw * 4);
+    const int64_t o_wst = so;
+    int32_t *ws = reinterpret_cast<int32_t *>(h + so);
+    ws[0] = 0;
+    for (int w = 0; w < nw; ++w) ws[w + 1] = ws[w] + wc[w];
+    so += a256((int64_t)(nw + 1) * 4);
+    const int64_t o_jst = so;
+    // device pointers
+    jd.seqs = reinterpret_cast<const uint8_t *>(d_ + o_seq);
+    jd.sub = reinterpret_cast<const int8_t *>(d_ + sub_off[i]);
+    jd.cells = reinterpret_cast<const uint32_t *>(d_ + off_cells[j.k]);
+    jd.hstart = reinterpret_cast<const int32_t *>(d_ + off_hs[j.k]);
+    jd.wcnt = reinterpret_cast<const int32_t *>(d_ + o_wcnt);
+    jd.wstart = reinterpret_cast<const int32_t *>(d_ + o_wst);
+    jd.jstatus = reinterpret_cast<int32_t *>(d_ + o_jst);
+    jd.qbase = jt[i];
+    jd.flags = reinterpret_cast<int32_t *>(d_ + off_flags) + jt[i];
+    int64_t bo = job_big[i];
+    jd.path = reinterpret_cast<uint8_t *>(d_ + bo);
+    bo += a256(std::max<int64_t>(p.total_len, 1));
+    jd.faces = reinterpret_cast<int32_t *>(d_ + bo);
+    bo += a256(std::max<int64_t>(p.face_elems * 4, 256));
+    jd.dir = reinterpret_cast<uint8_t *>(d_ + bo);
+    jd.score_out = reinterpret_cast<int64_t *>(d_ + off_score) + i;
+    jd.aln_len_out = reinterpret_cast<int64_t *>(d_ + off_len) + i;
+    jd.status_out = reinterpret_cast<int32_t *>(d_ + off_stat) + i;
+    jd.aln_out = reinterpret_cast<uint8_t *>(d_ + job_out[i]);
+    jd.aln_cap = sz[i].cap;
+    jd.trace = nullptr;
+    memcpy(&jd_all[i], &jd, sizeof(JobDev));
+    meta_[i].k = j.k;
+    meta_[i].cap = sz[i].cap;
+    meta_[i].aln_off = job_out[i] - off_out;
+  }
+
+  // ---- enqueue ----
+  bool ok = hipMemcpyAsync(d_, h, (size_t)in_bytes, hipMemcpyHostToDevice, stream_) == hipSuccess;
+  int grid = device_cu_count() * batch_occupancy(kc);
+  if (grid < 1) grid = 1;
+  ok = ok && launch_batch(kc, reinterpret_cast<const JobDev *>(d_ + off_jobs), nj,
+                          reinterpret_cast<const int64_t *>(d_ + off_jt),
+                          reinterpret_cast<int32_t *>(d_ + off_qjob),
+                          reinterpret_cast<int32_t *>(d_ + off_qtile), tiles,
+                          reinterpret_cast<int32_t *>(d_ + off_flags),
+                          reinterpret_cast<Ctrl *>(d_ + off_ctrl), grid, stream_) == 0;
+  ok = ok && hipMemcpyAsync(h_out_, d_ + off_out, (size_t)out_bytes, hipMemcpyDeviceToHost,
+                            stream_) == hipSuccess;
+  ok = ok && hipEventRecord(done_, stream_) == hipSuccess;
+  out_bytes_ = out_bytes;
+  out_off_ = off_out;
+  (void)off_score;
+  busy_ = true;
+  launch_status_ = ok ? MSA_OK : MSA_EDEVICE;
+  return launch_status_;
+}
+
+bool Launch::ready() {
+  if (!busy_) return true;
+  return hipEventQuery(done_) != hipErrorNotReady;
+}
+
+int Launch::wait() {
+  if (!busy_) return MSA_OK;
+  if (hipEventSynchronize(done_) != hipSuccess) launch_status_ = MSA_EDEVICE;
+  return launch_status_;
+}
+
+void Launch::result(int i, LaunchResult *out) const {
+  const int nj = (int)meta_.size();
+  const int64_t off_len = a256((int64_t)nj * 8);
+  const int64_t off_stat = off_len + a256((int64_t)nj * 8);
+  const int64_t *scores = reinterpret_cast<const int64_t *>(h_out_);
+  const int64_t *lens = reinterpret_cast<const int64_t *>(h_out_ + off_len);
+  const int32_t *stats = reinterpret_cast<const int32_t *>(h_out_ + off_stat);
+  out->k = meta_[i].k;
+  out->cap = meta_[i].cap;
+  out->status = launch_status_ != MSA_OK ? launch_status_ : stats[i];
+  out->score = out->status == MSA_OK ? scores[i] : 0;
+  out->aln_len = out->status == MSA_OK ? lens[i] : 0;
+  const uint8_t *rows = reinterpret_cast<const uint8_t *>(h_out_ + meta_[i].aln_off);
+  out->aln.assign(rows, rows + (size_t)meta_[i].k * meta_[i].cap);
+}
+
+void Launch::fill_result(int i, msa_result *out) const {
+  const int nj = (int)meta_.size();
+  const int64_t off_len = a256((int64_t)nj * 8);
+  const int64_t off_stat = off_len + a256((int64_t)nj * 8);
+  const int64_t *scores = reinterpret_cast<const int64_t *>(h_out_);
+  const int64_t *lens = reinterpret_cast<const int64_t *>(h_out_ + off_len);
+  const int32_t *stats = reinterpret_cast<const int32_t *>(h_out_ + off_stat);
+  const int st = launch_status_ != MSA_OK ? launch_status_ : stats[i];
+  out->status = st;
+  out->score = st == MSA_OK ? scores[i] : 0;
+  out->aln_len = st == MSA_OK ? lens[i] : 0;
+  if (st == MSA_OK && out->aln && out->aln_len > 0) {
+    const uint8_t *rows = reinterpret_cast<const uint8_t *>(h_out_ + meta_[i].aln_off);
+    for (int r = 0; r < meta_[i].k; ++r)
+      memcpy(out->aln + (int64_t)r * out->aln_cap, rows + (int64_t)r * meta_[i].cap,
+             (size_t)out->aln_len);
+  }
+}
+
+}  // namespace msa

@@ -1,0 +1,83 @@
+// msa_launch.h -- one batched persistent launch: a device arena holding many
+// jobs (descriptors, sequences, tile queue, flags, face planes, direction
+// blocks, outputs), staged from host jobs and run asynchronously on a stream.
+// Used by the batched call and by the server.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/msa_dp.h"
+#include "msa_plan.h"
+
+namespace msa {
+
+// Validation of one host job; returns MSA_OK or a status.
+int validate_job(const msa_job &j, int64_t aln_cap_needed_check = -1);
+
+// k class of the batched kernels: 0 for k = 2..4, 1 for k = 5..8.
+inline int kclass_of(int k) { return k <= 4 ? 0 : 1; }
+
+// Device bytes one job needs inside a launch arena.
+int64_t job_arena_bytes(const msa_job &j);
+
+struct LaunchResult {
+  int32_t status = MSA_OK;
+  int64_t score = 0;
+  int64_t aln_len = 0;
+  std::vector<uint8_t> aln;  // k rows of `cap` bytes
+  int64_t cap = 0;
+  int k = 0;
+};
+
+class Launch {
+ public:
+  Launch() = default;
+  ~Launch();
+  Launch(const Launch &) = delete;
+  Launch &operator=(const Launch &) = delete;
+
+  // Arena and stream set-up on the current device; arena of `bytes`.
+  int init(int64_t bytes);
+  int64_t capacity() const { return cap_; }
+
+  // Fixed bytes of a launch besides the jobs (control block, tables, queue).
+  static int64_t overhead_bytes(int njobs, int64_t ntiles_total);
+
+  // Stages the given valid jobs (all of one k class) and enqueues the launch.
+  // Returns MSA_OK, MSA_ENOMEM if they do not fit, or MSA_EDEVICE.
+  int start(const std::vector<const msa_job *> &jobs);
+  bool busy() const { return busy_; }
+  bool ready();            // launch finished (non-blocking)
+  int wait();              // block until finished
+  // After ready()/wait(): result of the i-th staged job.
+  void result(int i, LaunchResult *out) const;
+  void fill_result(int i, msa_result *out) const;
+  int njobs() const { return (int)meta_.size(); }
+  void release() { busy_ = false; meta_.clear(); }
+
+ private:
+  struct Meta {
+    int k = 0;
+    int64_t cap = 0;
+    int64_t aln_off = 0;  // offset of the rows in the host output image
+  };
+  int device_ = -1;
+  hipStream_t stream_ = nullptr;
+  hipEvent_t done_ = nullptr;
+  char *d_ = nullptr;
+  int64_t cap_ = 0;
+  char *h_in_ = nullptr;  // pinned staging (inputs)
+  int64_t h_in_cap_ = 0;
+  char *h_out_ = nullptr;  // pinned outputs
+  int64_t h_out_cap_ = 0;
+  int64_t out_bytes_ = 0;
+  int64_t out_off_ = 0;
+  std::vector<Meta> meta_;
+  bool busy_ = false;
+  int launch_status_ = MSA_OK;
+  int ensure_host(int64_t in_bytes, int64_t out_bytes);
+};
+
+}  // namespace msa

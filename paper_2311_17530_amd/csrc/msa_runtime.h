@@ -12,6 +12,10 @@ int launch_fill(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, hi
 int launch_traceback(const JobDev &jd, Ctrl *ctrl, hipStream_t s);
 int launch_export(const JobDev &jd, uint8_t *out, int64_t ncell, hipStream_t s);
 int fill_occupancy(int k);
+int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_jtiles,
+                 int32_t *qjob, int32_t *qtile, int64_t total, int32_t *flags, Ctrl *ctrl,
+                 int grid, hipStream_t s);
+int batch_occupancy(int kclass);
 
 // runtime (msa_runtime.cpp)
 int device_cu_count();

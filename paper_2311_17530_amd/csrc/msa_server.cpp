@@ -1,10 +1,292 @@
-// msa_server.cpp -- served path (placeholder).
+// msa_server.cpp -- served path: a request loop with continuous batching.
+//
+// Jobs are submitted at any time.  A worker thread keeps up to `max_inflight`
+// batched persistent launches running on separate streams; whenever a launch
+// slot is free it admits the oldest queued jobs (of one k class) that fit the
+// slot's share of the HBM budget, so requests that arrive while others run
+// start as soon as a slot and its memory free up, and launches overlap on the
+// device.  Finished results wait in a table until polled.
 #include <hip/hip_runtime.h>
 
-#include "../../include/msa_dp.h"
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
 
-extern "C" msa_server *msa_server_create(int64_t, int32_t, int32_t) { return nullptr; }
-extern "C" int msa_server_submit(msa_server *, const msa_job *, uint64_t *) { return MSA_EDEVICE; }
-extern "C" int msa_server_poll(msa_server *, uint64_t, msa_result *) { return MSA_EDEVICE; }
-extern "C" int msa_server_wait(msa_server *, uint64_t, msa_result *, int64_t) { return MSA_EDEVICE; }
-extern "C" void msa_server_destroy(msa_server *) {}
+#include "../../include/msa_dp.h"
+#include "msa_launch.h"
+
+namespace msa {
+int64_t default_budget();
+}
+using namespace msa;
+
+namespace {
+
+struct Pending {
+  uint64_t ticket = 0;
+  msa_job job{};
+  std::vector<uint8_t> seqbuf;
+  std::vector<int8_t> sub;
+  int64_t bytes = 0;
+  int64_t ntiles = 0;
+};
+
+struct Done {
+  int32_t status = MSA_OK;
+  int64_t score = 0;
+  int64_t aln_len = 0;
+  int k = 0;
+  int64_t cap = 0;
+  std::vector<uint8_t> aln;
+};
+
+struct Slot {
+  std::unique_ptr<Launch> launch;
+  std::vector<uint64_t> tickets;
+  std::vector<std::unique_ptr<Pending>> jobs;  // inputs stay alive while staged
+};
+
+}  // namespace
+
+struct msa_server {
+  std::mutex mu;
+  std::condition_variable cv_work;  // worker wake-up
+  std::condition_variable cv_done;  // results available
+  int device = 0;
+  int64_t budget = 0;
+  int64_t slot_bytes = 0;
+  int max_inflight = 1;
+  int max_jobs = 256;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::deque<std::unique_ptr<Pending>> queue;
+  std::map<uint64_t, Done> done;
+  std::map<uint64_t, int> running;  // ticket -> slot
+  std::vector<Slot> slots;
+  std::thread worker;
+  int init_status = MSA_OK;
+
+  void run();
+  bool admit(Slot &s);
+  void collect(Slot &s);
+};
+
+bool msa_server::admit(Slot &s) {
+  // FIFO admission: the oldest job fixes the k class; later jobs of the same
+  // class join while they fit the slot's arena and the per-launch job limit.
+  if (queue.empty()) return false;
+  const int kc = kclass_of(queue.front()->job.k);
+  std::vector<const msa_job *> grp;
+  int64_t used = 0, tiles = 0;
+  for (auto it = queue.begin(); it != queue.end() && (int)grp.size() < max_jobs;) {
+    Pending &p = **it;
+    if (kclass_of(p.job.k) != kc) {
+      ++it;
+      continue;
+    }
+    const int64_t need =
+        used + p.bytes + Launch::overhead_bytes((int)grp.size() + 1, tiles + p.ntiles);
+    if (need > s.launch->capacity()) {
+      if (grp.empty()) {  // cannot happen: oversized jobs are rejected at submit
+        done[p.ticket].status = MSA_ENOMEM;
+        it = queue.erase(it);
+        cv_done.notify_all();
+        continue;
+      }
+      break;
+    }
+    used += p.bytes;
+    tiles += p.ntiles;
+    grp.push_back(&p.job);
+    s.tickets.push_back(p.ticket);
+    s.jobs.push_back(std::move(*it));
+    it = queue.erase(it);
+  }
+  if (grp.empty()) return false;
+  const int rc = s.launch->start(grp);
+  for (uint64_t t : s.tickets) running[t] = 0;
+  if (rc != MSA_OK) {
+    for (uint64_t t : s.tickets) {
+      done[t].status = rc;
+      running.erase(t);
+    }
+    s.tickets.clear();
+    s.jobs.clear();
+    s.launch->release();
+    cv_done.notify_all();
+    return false;
+  }
+  return true;
+}
+
+void msa_server::collect(Slot &s) {
+  s.launch->wait();
+  for (size_t i = 0; i < s.tickets.size(); ++i) {
+    LaunchResult r;
+    s.launch->result((int)i, &r);
+    Done &d = done[s.tickets[i]];
+    d.status = r.status;
+    d.score = r.score;
+    d.aln_len = r.aln_len;
+    d.k = r.k;
+    d.cap = r.cap;
+    d.aln.swap(r.aln);
+    running.erase(s.tickets[i]);
+  }
+  s.tickets.clear();
+  s.jobs.clear();
+  s.launch->release();
+  cv_done.notify_all();
+}
+
+void msa_server::run() {
+  if (hipSetDevice(device) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(mu);
+    init_status = MSA_EDEVICE;
+    return;
+  }
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    bool progress = false;
+    for (auto &s : slots) {
+      if (s.launch->busy() && s.launch->ready()) {
+        collect(s);
+        progress = true;
+      }
+    }
+    for (auto &s : slots) {
+      if (!s.launch->busy() && !queue.empty() && !stop) progress |= admit(s);
+    }
+    bool any_busy = false;
+    for (auto &s : slots) any_busy |= s.launch->busy();
+    if (stop && !any_busy) break;
+    if (!progress) {
+      if (any_busy)  // poll the device for finished launches
+        cv_work.wait_for(lk, std::chrono::microseconds(50));
+      else
+        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+    }
+  }
+  // shutting down: jobs never admitted are reported as such
+  for (auto &p : queue) done[p->ticket].status = MSA_ESHUTDOWN;
+  queue.clear();
+  cv_done.notify_all();
+}
+
+extern "C" msa_server *msa_server_create(int64_t hbm_budget_bytes, int32_t max_inflight,
+                                         int32_t max_jobs_per_launch) {
+  if (max_inflight < 1 || max_inflight > 16 || max_jobs_per_launch < 1) return nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::unique_ptr<msa_server> s(new msa_server());
+  s->device = dev;
+  s->budget = hbm_budget_bytes > 0 ? hbm_budget_bytes : default_budget();
+  s->max_inflight = max_inflight;
+  s->max_jobs = max_jobs_per_launch;
+  s->slot_bytes = s->budget / max_inflight;
+  s->slots.resize(max_inflight);
+  for (auto &sl : s->slots) {
+    sl.launch.reset(new Launch());
+    if (sl.launch->init(s->slot_bytes) != MSA_OK) return nullptr;
+  }
+  s->worker = std::thread([p = s.get()] { p->run(); });
+  return s.release();
+}
+
+extern "C" int msa_server_submit(msa_server *srv, const msa_job *job, uint64_t *ticket) {
+  if (!srv || !job || !ticket) return MSA_EINVAL;
+  int rc = validate_job(*job);
+  if (rc) return rc;
+  std::unique_ptr<Pending> p(new Pending());
+  int64_t total = 0;
+  for (int d = 0; d < job->k; ++d) total += job->lens[d];
+  p->seqbuf.resize((size_t)std::max<int64_t>(total, 1));
+  p->sub.assign(job->submat, job->submat + (size_t)job->alpha * job->alpha);
+  p->job = *job;
+  int64_t off = 0;
+  for (int d = 0; d < job->k; ++d) {
+    if (job->lens[d] > 0) std::memcpy(p->seqbuf.data() + off, job->seqs[d], (size_t)job->lens[d]);
+    p->job.seqs[d] = p->seqbuf.data() + off;
+    off += job->lens[d];
+  }
+  p->job.submat = p->sub.data();
+  p->bytes = job_arena_bytes(p->job);
+  Plan pl;
+  make_plan(job->lens, job->k, &pl);
+  p->ntiles = pl.ntiles;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (srv->stop) return MSA_ESHUTDOWN;
+  if (srv->init_status != MSA_OK) return srv->init_status;
+  if (p->bytes + Launch::overhead_bytes(1, p->ntiles) > srv->slot_bytes) return MSA_ENOMEM;
+  p->ticket = srv->next_ticket++;
+  *ticket = p->ticket;
+  srv->queue.push_back(std::move(p));
+  srv->cv_work.notify_all();
+  return MSA_OK;
+}
+
+static int take_result(msa_server *srv, uint64_t ticket, msa_result *out) {
+  auto it = srv->done.find(ticket);
+  if (it == srv->done.end()) return MSA_EAGAIN;
+  Done &d = it->second;
+  out->status = d.status;
+  out->score = d.status == MSA_OK ? d.score : 0;
+  out->aln_len = d.status == MSA_OK ? d.aln_len : 0;
+  if (d.status == MSA_OK && d.aln_len > 0) {
+    if (!out->aln || out->aln_cap < d.aln_len) {
+      out->status = MSA_EINVAL;
+      srv->done.erase(it);
+      return MSA_EINVAL;
+    }
+    for (int r = 0; r < d.k; ++r)
+      std::memcpy(out->aln + (int64_t)r * out->aln_cap, d.aln.data() + (int64_t)r * d.cap,
+                  (size_t)d.aln_len);
+  }
+  const int st = d.status;
+  srv->done.erase(it);
+  return st;
+}
+
+static bool known_ticket(msa_server *srv, uint64_t ticket) {
+  if (srv->done.count(ticket) || srv->running.count(ticket)) return true;
+  for (auto &p : srv->queue)
+    if (p->ticket == ticket) return true;
+  return false;
+}
+
+extern "C" int msa_server_poll(msa_server *srv, uint64_t ticket, msa_result *out) {
+  if (!srv || !out) return MSA_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (!known_ticket(srv, ticket)) return MSA_EINVAL;
+  return take_result(srv, ticket, out);
+}
+
+extern "C" int msa_server_wait(msa_server *srv, uint64_t ticket, msa_result *out,
+                               int64_t timeout_us) {
+  if (!srv || !out) return MSA_EINVAL;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  if (!known_ticket(srv, ticket)) return MSA_EINVAL;
+  auto ready = [&] { return srv->done.count(ticket) > 0; };
+  if (timeout_us < 0)
+    srv->cv_done.wait(lk, ready);
+  else if (!srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
+    return MSA_EAGAIN;
+  return take_result(srv, ticket, out);
+}
+
+extern "C" void msa_server_destroy(msa_server *srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+    srv->cv_work.notify_all();
+  }
+  if (srv->worker.joinable()) srv->worker.join();
+  delete srv;
+}

@@ -1,0 +1,182 @@
+"""GPU tests of the batched and served paths.
+
+Every job's result must equal (a) the oracle and (b) the same job run alone
+through the plain path, bit for bit.  The 4096-job workload (k in {3,4},
+lengths 16..160, DNA and protein) runs in the same batched launches the
+benchmark times; sampled jobs are checked against the oracle one by one and
+every job is checked for properties that hold at any size (the returned
+alignment's sum-of-pairs score equals the returned score, rows strip to the
+inputs, the plain path agrees on sampled jobs).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import paper_2311_17530_amd as msa
+from msa_inputs import batch_jobs, dna_scoring, protein_scoring, served_jobs
+from oracle import oracle_align
+
+pytestmark = pytest.mark.gpu
+
+GAP = 0xFF
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    msa.lib()
+    yield
+
+
+def sp_numpy(rows, sub, gap):
+    rows = np.asarray(rows, dtype=np.int64)
+    k, L = rows.shape
+    sub = np.asarray(sub, dtype=np.int64)
+    s = 0
+    for i in range(k):
+        for j in range(i + 1, k):
+            a, b = rows[i], rows[j]
+            ga, gb = a == GAP, b == GAP
+            both = ~ga & ~gb
+            s += int(sub[a[both], b[both]].sum())
+            s += gap * int((ga ^ gb).sum())
+    return s
+
+
+def check_props(seqs, sub, gap, score, rows):
+    k = len(seqs)
+    assert rows.shape[0] == k
+    for i in range(k):
+        assert np.array_equal(rows[i][rows[i] != GAP], np.asarray(seqs[i]))
+    assert sp_numpy(rows, sub, gap) == score
+
+
+def small_mixed(seed, n):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    jobs = []
+    for _ in range(n):
+        k = int(rng.integers(2, 6))
+        prot = bool(rng.integers(0, 2))
+        sub, gap = protein_scoring() if prot else dna_scoring()
+        nmax = {2: 70, 3: 30, 4: 14, 5: 8}[k]
+        seqs = [rng.integers(0, sub.shape[0], size=int(rng.integers(0, nmax + 1))).astype(np.uint8)
+                for _ in range(k)]
+        jobs.append((seqs, sub, gap))
+    return jobs
+
+
+def test_batch_matches_oracle_and_plain_path():
+    jobs = small_mixed(5000, 40)
+    say("batch of", len(jobs))
+    res = msa.align_batch(jobs)
+    for (seqs, sub, gap), (st, score, rows) in zip(jobs, res):
+        assert st == msa.MSA_OK
+        s0, r0, _ = oracle_align(seqs, sub, gap)
+        assert score == s0 and np.array_equal(rows, r0), [len(s) for s in seqs]
+        s1, r1 = msa.align(seqs, sub, gap)
+        assert s1 == score and np.array_equal(r1, rows)
+
+
+def test_batch_small_budget_splits_launches():
+    jobs = small_mixed(5001, 30)
+    say("batch with small budget")
+    full = msa.align_batch(jobs)
+    split = msa.align_batch(jobs, hbm_budget_bytes=24 << 20)
+    for a, b in zip(full, split):
+        assert a[0] == b[0] == msa.MSA_OK
+        assert a[1] == b[1] and np.array_equal(a[2], b[2])
+
+
+def test_batch_reports_per_job_errors():
+    sub, gap = dna_scoring()
+    good = [np.array([0, 1, 2, 3], np.uint8), np.array([0, 2, 3], np.uint8)]
+    bad = [np.array([0, 9], np.uint8), np.array([1], np.uint8)]  # code >= alpha
+    res = msa.align_batch([(good, sub, gap), (bad, sub, gap), (good * 2, sub, gap)])
+    assert res[0][0] == msa.MSA_OK and res[2][0] == msa.MSA_OK
+    assert res[1][0] == msa.MSA_EINVAL
+    s0, r0, _ = oracle_align(good, sub, gap)
+    assert res[0][1] == s0 and np.array_equal(res[0][2], r0)
+
+
+def test_batch_4096_workload():
+    jobs = batch_jobs(4096)
+    tuples = [(j.seqs, j.sub, j.gap) for j in jobs]
+    say("batch 4096 jobs, cells", sum(j.cells for j in jobs))
+    t0 = time.time()
+    res = msa.align_batch(tuples)
+    say("batch 4096 done in %.2f s" % (time.time() - t0))
+    assert all(r[0] == msa.MSA_OK for r in res)
+    for (seqs, sub, gap), (_, score, rows) in zip(tuples, res):
+        check_props(seqs, sub, gap, score, rows)
+    # oracle on the smallest jobs and a few random ones
+    order = np.argsort([j.cells for j in jobs])
+    rng = np.random.Generator(np.random.PCG64(77))
+    sample = list(order[:6]) + [int(x) for x in rng.choice(order[:2048], size=4, replace=False)]
+    for i in sample:
+        seqs, sub, gap = tuples[i]
+        say("oracle check job", i, [len(s) for s in seqs])
+        s0, r0, _ = oracle_align(seqs, sub, gap)
+        assert res[i][1] == s0 and np.array_equal(res[i][2], r0)
+    for i in sample[:4]:
+        s1, r1 = msa.align(*tuples[i])
+        assert s1 == res[i][1] and np.array_equal(r1, res[i][2])
+
+
+def test_server_alone_equals_mixed():
+    jobs = small_mixed(6000, 24)
+    probe = jobs[3]
+    with msa.Server(hbm_budget_bytes=1 << 30, max_inflight=3, max_jobs_per_launch=8) as srv:
+        t = srv.submit(*probe)
+        alone = srv.wait(t, 30_000_000)
+        tickets = [srv.submit(*j) for j in jobs]
+        mixed = [srv.wait(t, 30_000_000) for t in tickets]
+    assert alone[0] == msa.MSA_OK
+    assert mixed[3][1] == alone[1] and np.array_equal(mixed[3][2], alone[2])
+    for (seqs, sub, gap), (st, score, rows) in zip(jobs, mixed):
+        assert st == msa.MSA_OK
+        s0, r0, _ = oracle_align(seqs, sub, gap)
+        assert score == s0 and np.array_equal(rows, r0)
+
+
+def test_server_stream_of_served_jobs():
+    jobs = served_jobs(200, seed=5)
+    with msa.Server(max_inflight=4, max_jobs_per_launch=32) as srv:
+        tickets = []
+        for j in jobs:
+            tickets.append(srv.submit(j.seqs, j.sub, j.gap))
+        out = [srv.wait(t, 60_000_000) for t in tickets]
+    assert all(o is not None and o[0] == msa.MSA_OK for o in out)
+    for j, (_, score, rows) in zip(jobs, out):
+        check_props(j.seqs, j.sub, j.gap, score, rows)
+    small = sorted(range(len(jobs)), key=lambda i: jobs[i].cells)[:5]
+    for i in small:
+        s0, r0, _ = oracle_align(jobs[i].seqs, jobs[i].sub, jobs[i].gap)
+        assert out[i][1] == s0 and np.array_equal(out[i][2], r0)
+
+
+def test_server_errors_and_shutdown():
+    sub, gap = dna_scoring()
+    with msa.Server(hbm_budget_bytes=64 << 20, max_inflight=2) as srv:
+        with pytest.raises(msa.MsaError) as e:
+            srv.submit([np.array([0, 9], np.uint8), np.array([1], np.uint8)], sub, gap)
+        assert e.value.status == msa.MSA_EINVAL
+        with pytest.raises(msa.MsaError) as e:  # alone larger than a slot's budget
+            big = [np.zeros(400, np.uint8)] * 4
+            srv.submit(big, sub, gap)
+        assert e.value.status == msa.MSA_ENOMEM
+        assert msa.lib().msa_server_poll(srv.h, 987654321, None) == msa.MSA_EINVAL
+        t = srv.submit([np.array([0, 1], np.uint8), np.array([1], np.uint8)], sub, gap)
+        r = srv.wait(t, 30_000_000)
+        assert r[0] == msa.MSA_OK
+    # destroy with work still queued or running must not hang
+    srv = msa.Server(max_inflight=2)
+    for _ in range(10):
+        srv.submit(*small_mixed(6100, 1)[0])
+    srv.close()
