@@ -16,7 +16,11 @@ already resident in HBM.  Prints one JSON line:
                full k=3 / 512 alignment
 
 The same numbers for the k=4 / 128 workload (129^4 cells) are reported under
-"extra".  Only one GPU is used: --gpus above 1 is rejected.
+"extra"; "batched" gives jobs/s of the 4096-job workload through the batched
+persistent launches (beside sequential plain calls), "served" the saturated
+throughput and p50/p99 latency of a 20000-job Poisson stream through the
+server at 0.7 times that rate.  Only one GPU is used: --gpus above 1 is
+rejected.
 """
 from __future__ import annotations
 
@@ -81,6 +85,89 @@ def time_workload(name, steps, warmup):
         tile_edge=msa.tile_edge(job.k))
 
 
+def bench_batched(n_jobs=4096, n_plain=256):
+    """Jobs/s of the batched persistent launches on the 4096-job workload
+    (host buffers in and out, staging included), next to the same jobs run one
+    at a time through the plain path (first n_plain jobs)."""
+    import paper_2311_17530_amd as msa
+    from msa_inputs import batch_jobs
+
+    jobs = batch_jobs(n_jobs)
+    tuples = [(j.seqs, j.sub, j.gap) for j in jobs]
+    msa.align_batch(tuples[:64])  # warm-up: arena allocation, code load
+    t0 = time.perf_counter()
+    res = msa.align_batch(tuples)
+    dt = time.perf_counter() - t0
+    ok = sum(r[0] == 0 for r in res)
+    cells = sum(j.cells for j in jobs)
+    msa.align(*tuples[0])
+    t1 = time.perf_counter()
+    for t in tuples[:n_plain]:
+        msa.align(*t)
+    dtp = time.perf_counter() - t1
+    return {"jobs": n_jobs, "ok": ok, "seconds": round(dt, 4),
+            "jobs_per_s": round(n_jobs / dt, 2), "gcups": round(cells / dt / 1e9, 3),
+            "sequential_plain_jobs_per_s": round(n_plain / dtp, 2),
+            "sequential_plain_sample": f"first {n_plain} jobs, one msa_dp_align call each",
+            "speedup_vs_sequential": round((n_jobs / dt) / (n_plain / dtp), 2)}
+
+
+def bench_served(n_jobs=20000, load=0.7, max_inflight=4, max_jobs=256):
+    """Served path: saturated throughput X (all jobs submitted at once), then a
+    Poisson stream at load * X with per-job latency from arrival to result."""
+    import threading
+
+    import paper_2311_17530_amd as msa
+    from msa_inputs import poisson_arrivals, served_jobs
+
+    jobs = served_jobs(n_jobs)
+    cells = sum(j.cells for j in jobs)
+    with msa.Server(max_inflight=max_inflight, max_jobs_per_launch=max_jobs) as srv:
+        for j in jobs[:32]:  # warm-up
+            srv.wait(srv.submit(j.seqs, j.sub, j.gap))
+        t0 = time.perf_counter()
+        tickets = [srv.submit(j.seqs, j.sub, j.gap) for j in jobs]
+        for t in tickets:
+            srv.wait(t)
+        sat = n_jobs / (time.perf_counter() - t0)
+
+        rate = load * sat
+        arr = poisson_arrivals(n_jobs, rate)
+        tick = [None] * n_jobs
+        t_sub = np.zeros(n_jobs)
+        t_done = np.zeros(n_jobs)
+        status = np.zeros(n_jobs, dtype=np.int64)
+        ready = threading.Semaphore(0)
+
+        def waiter():
+            for i in range(n_jobs):
+                ready.acquire()
+                r = srv.wait(tick[i])
+                t_done[i] = time.perf_counter()
+                status[i] = r[0]
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        start = time.perf_counter()
+        for i, j in enumerate(jobs):
+            now = time.perf_counter() - start
+            if arr[i] > now:
+                time.sleep(arr[i] - now)
+            t_sub[i] = time.perf_counter()
+            tick[i] = srv.submit(j.seqs, j.sub, j.gap)
+            ready.release()
+        th.join()
+        span = t_done.max() - start
+    lat = (t_done - t_sub) * 1e3
+    return {"jobs": n_jobs, "ok": int((status == 0).sum()),
+            "saturated_jobs_per_s": round(sat, 2), "saturated_gcups": round(cells / (n_jobs / sat) / 1e9, 3),
+            "arrival_rate_per_s": round(rate, 2), "load": load,
+            "jobs_per_s": round(n_jobs / span, 2),
+            "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+            "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+            "max_inflight_launches": max_inflight, "max_jobs_per_launch": max_jobs}
+
+
 def cpu_baseline():
     from msa_inputs import workload
     from oracle import build_oracle_lib, oracle_align
@@ -117,6 +204,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (counter calibration)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 4096-job batch")
+    ap.add_argument("--no-served", action="store_true", help="skip the 20000-job server run")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs each alignment on a "
@@ -158,11 +247,15 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_INT32_TOPS, 2), "unit": "Tops/s",
                      "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
-                     "kernel": "fill_kernel<3,64>",
+                     "kernel": "fill_kernel<3,256,2> (k=3, T=16, four waves per tile)",
                      "ops_per_launch": 2 * main_r["neighbour_updates"]},
         "extra": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                       for kk, vv in v.items()} for k, v in extra.items()},
     }
+    if not a.no_batched:
+        line["batched"] = bench_batched()
+    if not a.no_served:
+        line["served"] = bench_served()
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
