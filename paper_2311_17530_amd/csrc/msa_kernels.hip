@@ -28,44 +28,55 @@ enum { ST_OK = 0, ST_EINVAL = -1, ST_EDEVICE = -4 };
 
 constexpr int kSubLds = 32;  // substitution matrices up to 32x32 live in LDS
 
+// LDS word strides of the tile with halo, dimension k-1 last (stride 1).  Each
+// stride exceeds T times the sum of the strides after it, so every cell of the
+// (T+1)^k box has its own word.  Within that freedom they are chosen so that
+// one sweep step (consecutive lines on consecutive lanes) reads and writes
+// distinct LDS banks for k <= 4.
+template <int K> struct Strides;
+template <> struct Strides<2> { static constexpr int v[2] = {34, 1}; };
+template <> struct Strides<3> { static constexpr int v[3] = {305, 18, 1}; };
+template <> struct Strides<4> { static constexpr int v[4] = {801, 89, 10, 1}; };
+template <> struct Strides<5> { static constexpr int v[5] = {1296, 216, 36, 6, 1}; };
+template <> struct Strides<6> { static constexpr int v[6] = {1024, 256, 64, 16, 4, 1}; };
+template <> struct Strides<7> { static constexpr int v[7] = {733, 244, 81, 27, 9, 3, 1}; };
+template <> struct Strides<8> { static constexpr int v[8] = {2197, 733, 244, 81, 27, 9, 3, 1}; };
+
 template <int K>
 struct Cfg {
   static constexpr int T = tile_edge_for_k(K);
-  static constexpr int E = T + 1;          // LDS edge including the halo
-  // Row pitch of the LDS tile, padded to an even number of words: cells that
-  // are neighbours on a hyperplane (one step up in one dimension, one step down
-  // in the last) then differ by an odd number of words, so a wave reading
-  // them spreads over all LDS banks.
-  static constexpr int RP = (E % 2 == 0) ? E : E + 1;
-  static constexpr int NS = (K == 1 ? 1 : ipow(E, K - 2) * RP) * E;  // LDS score words
-  static constexpr int NC = ipow(T, K);    // cells of a full tile
+  static constexpr int E = T + 1;           // LDS edge including the halo
+  static constexpr int KL = K - 1;          // sweep dimension: one lane per line along it
+  static constexpr int L = ipow(T, K - 1);  // lines of a full tile
+  static constexpr int NC = ipow(T, K);     // cells of a full tile
   static constexpr int NP = K * (K - 1) / 2;
-  static constexpr int B = bits_for(T - 1);
   static constexpr int M = (1 << K) - 1;
-  static constexpr int H = K * (T - 1) + 1;  // hyperplanes of a full tile
+  static constexpr int ML = (1 << (K - 1)) - 1;  // neighbour masks over dimensions 0..k-2
   static constexpr int DBS = (NC + 15) / 16 * 16;
-  static constexpr int hwidth(int h) {  // cells of a full tile on hyperplane h
-    int cnt[K * 32] = {};
-    cnt[0] = 1;
-    int top = 0;
-    for (int d = 0; d < K; ++d) {  // convolve with (1 + x + ... + x^{T-1})
-      int nxt[K * 32] = {};
-      for (int a = 0; a <= top; ++a)
-        for (int b = 0; b < T; ++b) nxt[a + b] += cnt[a];
-      top += T - 1;
-      for (int a = 0; a <= top; ++a) cnt[a] = nxt[a];
+  // Direction bytes of a line accumulate in registers (T/4 words per lane) and
+  // are stored straight to the tile's block when T is a multiple of 4;
+  // otherwise they are staged in LDS.
+  static constexpr bool REGDIR = T % 4 == 0;
+  // Neighbours one step back along the line are the values the lane read (or
+  // wrote) in the previous step: carried in registers for k <= 4.
+  static constexpr bool CARRY = K <= 4;
+  static constexpr int sstride(int i) { return Strides<K>::v[i]; }
+  static constexpr int ns() {
+    int s = 0;
+    for (int i = 0; i < K; ++i) s += sstride(i);
+    return T * s + 1;
+  }
+  static constexpr int NS = ns();  // LDS score words
+  static constexpr bool strides_ok() {
+    if (sstride(K - 1) != 1) return false;
+    for (int i = 0; i < K - 1; ++i) {
+      int s = 0;
+      for (int j = i + 1; j < K; ++j) s += sstride(j);
+      if (sstride(i) <= T * s) return false;
     }
-    return h <= top ? cnt[h] : 0;
+    return true;
   }
-  static constexpr int maxw() {
-    int m = 0;
-    for (int h = 0; h < H; ++h) m = hwidth(h) > m ? hwidth(h) : m;
-    return m;
-  }
-  static constexpr int MAXW = maxw();
-  static constexpr int sstride(int i) {  // LDS strides: 1, RP, RP*E, RP*E^2, ...
-    return i == K - 1 ? 1 : RP * ipow(E, K - 2 - i);
-  }
+  static_assert(strides_ok(), "LDS strides must give every cell of the tile its own word");
   static constexpr int dstride(int i) { return ipow(T, K - 1 - i); }
   static constexpr int pair_index(int i, int j) {  // i < j
     return i * (2 * K - i - 1) / 2 + (j - i - 1);
@@ -78,41 +89,13 @@ struct Cfg {
   }
 };
 
-
-// Hyperplane starts of a full tile (prefix sums of hwidth), a compile-time
-// table in constant memory: read with wave-uniform (scalar) loads, so no LDS
-// round trip precedes the per-hyperplane cell reads.
-template <int K>
-struct HsTab {
-  int32_t v[Cfg<K>::H + 2];
-};
-template <int K>
-constexpr HsTab<K> make_hs() {
-  HsTab<K> t{};
-  int acc = 0;
-  for (int h = 0; h < Cfg<K>::H; ++h) {
-    t.v[h] = acc;
-    acc += Cfg<K>::hwidth(h);
-  }
-  t.v[Cfg<K>::H] = acc;
-  t.v[Cfg<K>::H + 1] = acc;
-  return t;
-}
-template <int K>
-__constant__ HsTab<K> kHs = make_hs<K>();
-
-static_assert(make_hs<3>().v[Cfg<3>::H] == Cfg<3>::NC, "hyperplane widths sum to T^k");
-static_assert(make_hs<4>().v[Cfg<4>::H] == Cfg<4>::NC, "hyperplane widths sum to T^k");
-
 template <int K>
 struct Smem {
-  int32_t S[Cfg<K>::NS];                          // tile keys with halo
-  int32_t PT[Cfg<K>::NP * Cfg<K>::T * Cfg<K>::T];  // pair scores << k
-  int32_t SUB[kSubLds * kSubLds];                 // substitution matrix << k
-  uint16_t CELLS[Cfg<K>::NC];                     // hyperplane-sorted cells
-  int32_t HS[Cfg<K>::H + 1];                      // hyperplane starts
-  uint8_t RES[K * Cfg<K>::T];                     // residues of the tile
-  alignas(16) uint8_t DIRB[Cfg<K>::DBS];          // direction bytes
+  int32_t S[Cfg<K>::NS];                                // tile keys with halo
+  int32_t PT[Cfg<K>::NP * Cfg<K>::T * Cfg<K>::T];       // pair scores << k
+  int32_t SUB[kSubLds * kSubLds];                       // substitution matrix << k
+  uint8_t RES[K * Cfg<K>::T];                           // residues of the tile
+  alignas(16) uint8_t DIRB[Cfg<K>::REGDIR ? 16 : Cfg<K>::DBS];  // staged direction bytes
 };
 
 __device__ inline int64_t wall_now() { return (int64_t)wall_clock64(); }
@@ -128,6 +111,12 @@ __device__ inline int64_t wall_now() { return (int64_t)wall_clock64(); }
 
 // Watchdog for dependency waits: wall_clock64 runs at a fixed 100 MHz.
 constexpr int64_t kWaitLimitTicks = 200000000;  // 2 s
+// Longest pause between two polls of a dependency wait, in units of
+// s_sleep 2 (about 128 clocks each).
+#ifndef MSA_MAX_NAP
+#define MSA_MAX_NAP 16
+#endif
+constexpr int kMaxNap = MSA_MAX_NAP;
 
 // Face-plane accesses and completion flags.
 //  SYNC 1: plain face loads/stores, agent-scope release fence before the flag,
@@ -151,16 +140,22 @@ __device__ inline void face_store(int32_t *p, int32_t v) {
     *p = v;
 }
 
-// Per-launch constant tables into LDS (done once per persistent workgroup).
+// Per-launch constant table into LDS (done once per persistent workgroup).
 template <int K, int NT>
 __device__ void load_tables(const JobDev &jd, int alpha, Smem<K> &sm) {
-  using C = Cfg<K>;
   const int tid = threadIdx.x;
-  for (int h = tid; h <= C::H; h += NT) sm.HS[h] = jd.hstart[h];
-  for (int e = tid; e < C::NC; e += NT) sm.CELLS[e] = (uint16_t)jd.cells[e];
   if (alpha <= kSubLds)
     for (int e = tid; e < alpha * alpha; e += NT)
       sm.SUB[(e / alpha) * kSubLds + e % alpha] = ((int32_t)jd.sub[e]) * (1 << K);
+}
+
+// Appends one byte at the top of a little-endian register queue of NR words
+// (the oldest byte leaves at the bottom).
+template <int NR>
+__device__ inline void shift_in(uint32_t (&d)[NR], uint32_t byte) {
+#pragma unroll
+  for (int r = 0; r < NR - 1; ++r) d[r] = (d[r] >> 8) | (d[r + 1] << 24);
+  d[NR - 1] = (d[NR - 1] >> 8) | (byte << 24);
 }
 
 // ---------------------------------------------------------------------------
@@ -173,62 +168,31 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
   constexpr int T = C::T;
   constexpr int E = C::E;
   constexpr int M = C::M;
-  const int tid = threadIdx.x;
+  constexpr int KL = C::KL;
+  // The thread index is made opaque here so that values derived from it are
+  // recomputed per tile instead of being hoisted out of the persistent loop
+  // (which keeps them live in registers across every phase).
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
 
   int c[K], lo[K], ext[K];
-  bool full = true, origin = true, corner = true;
+  bool origin = true, corner = true;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     c[i] = (tile / jd.tstride[i]) % jd.P[i];
     lo[i] = c[i] == 0 ? 0 : (c[i] - 1) * T + 1;
     ext[i] = c[i] == 0 ? 1 : min(T, jd.n[i] - (c[i] - 1) * T);
-    full = full && ext[i] == T;
     origin = origin && c[i] == 0;
     corner = corner && c[i] == jd.P[i] - 1;
   }
-
-  // ---- wait for the k face predecessors (diagonal ones are implied) ----
-  // Wave 0 polls: lane i reads the flag of tile c - e_i.  The loop condition is
-  // a wave vote and every exit test is wave-uniform, so the wave never splits;
-  // the other waves wait at the barrier below.
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) >> 6;
-  if (wave == 0) {
-    const int32_t *f = jd.flags;
-    bool need = false;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-      if (tid == i && c[i] > 0) {
-        need = true;
-        f = jd.flags + (tile - jd.tstride[i]);
-      }
-    }
-    const int64_t t0 = wall_now();
-    MSA_TRACE_POINT(jd, tile, 0);
-    for (;;) {
-      bool ok = true;
-      if (need) ok = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
-      if (__all(ok)) break;
-      const int st = __builtin_amdgcn_readfirstlane(
-          __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      if (st == ST_EDEVICE) break;
-      if (wall_now() - t0 > kWaitLimitTicks) {
-        atomicCAS(&ctrl->status, ST_OK, ST_EDEVICE);  // all lanes: idempotent
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-  }
-  __syncthreads();
-  if constexpr (SYNC != 2)
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  else
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 
-  MSA_TRACE_POINT(jd, tile, 1);
+  MSA_TRACE_POINT(jd, tile, 0);
   // ---- residues of this tile (v = lo + q; sequence index v - 1) ----
-  // Loads are issued unconditionally from clamped in-range addresses (no
-  // per-lane branch around a load, so all of them are in flight together); the
-  // values are selected and checked afterwards.
+  // They do not depend on the predecessor tiles, so they and the pair tables
+  // are prepared before the dependency wait.  Loads are issued
+  // unconditionally from clamped in-range addresses; the values are selected
+  // and checked afterwards.
   {
     int r[K];
     const bool any_seq = jd.total_len > 0;  // uniform: no sequence bytes at all
@@ -249,7 +213,67 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     }
     if (bad) atomicCAS(jstatus, ST_OK, ST_EINVAL);
   }
+  __syncthreads();
 
+  // ---- pair tables: PT[p][a][b] = sub(r_i(a), r_j(b)) << k ----
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+#pragma unroll
+    for (int j = i + 1; j < K; ++j) {
+      constexpr int TT = T * T;
+      int32_t *pt = sm.PT + C::pair_index(i, j) * TT;
+      for (int idx = tid; idx < TT; idx += NT) {
+        const int a = sm.RES[i * T + idx / T];
+        const int b = sm.RES[j * T + idx % T];
+        pt[idx] = alpha <= kSubLds ? sm.SUB[a * kSubLds + b]
+                                   : ((int32_t)jd.sub[a * alpha + b]) * (1 << K);
+      }
+    }
+  }
+
+  // ---- wait for the k face predecessors (diagonal ones are implied) ----
+  // Wave 0 polls: lane i reads the flag of tile c - e_i until it has seen it
+  // (a flag never goes back within a launch), so satisfied lanes stop loading.
+  // The loop condition is a wave vote and every exit test is wave-uniform, so
+  // the wave never splits; the other waves wait at the barrier below.  Polls
+  // back off exponentially up to kMaxNap sleeps: tiles popped far ahead of the
+  // running wavefront would otherwise flood the memory system with
+  // device-coherent loads and slow every tile's halo and face traffic.
+  if (wave == 0) {
+    const int32_t *f = jd.flags;
+    bool need = false;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (tid == i && c[i] > 0) {
+        need = true;
+        f = jd.flags + (tile - jd.tstride[i]);
+      }
+    }
+    const int64_t t0 = wall_now();
+    int nap = 1;
+    for (int it = 0;; ++it) {
+      if (need) need = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch;
+      if (!__any(need)) break;
+      if ((it & 7) == 7) {
+        const int st = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (st == ST_EDEVICE) break;
+        if (wall_now() - t0 > kWaitLimitTicks) {
+          atomicCAS(&ctrl->status, ST_OK, ST_EDEVICE);  // all lanes: idempotent
+          break;
+        }
+      }
+      for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(2);
+      nap = nap < kMaxNap ? 2 * nap : kMaxNap;
+    }
+  }
+  __syncthreads();
+  if constexpr (SYNC != 2)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  else
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+
+  MSA_TRACE_POINT(jd, tile, 1);
   // ---- halo: layer l_i = 0 along each dimension ----
   // Loads first, LDS stores after: for small k every face load of every
   // dimension is in flight at once (one memory round trip per tile).
@@ -304,125 +328,212 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
   __syncthreads();
 
   MSA_TRACE_POINT(jd, tile, 2);
-  // ---- pair tables: PT[p][a][b] = sub(r_i(a), r_j(b)) << k ----
+  // ---- sweep ----
+  // Lane l owns line l = (q_0 .. q_{k-2}) of the tile and computes its cell
+  // (line, t) at local hyperplane h = q_0 + ... + q_{k-2} + t, one cell per
+  // step, with a barrier between steps.  The cell's LDS word is idx0 + t, so
+  // the 2^k - 1 neighbours are fixed offsets below it; consecutive lanes hold
+  // consecutive lines, whose words fall in distinct banks (strides above).
+  constexpr int L = C::L;
+  constexpr int U = (L + NT - 1) / NT;  // lines per lane
+  constexpr int NR = C::REGDIR ? T / 4 : 1;
+  uint32_t dr[U][NR];
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
+  for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int j = i + 1; j < K; ++j) {
-      constexpr int TT = T * T;
-      int32_t *pt = sm.PT + C::pair_index(i, j) * TT;
-      for (int idx = tid; idx < TT; idx += NT) {
-        const int a = sm.RES[i * T + idx / T];
-        const int b = sm.RES[j * T + idx % T];
-        pt[idx] = alpha <= kSubLds ? sm.SUB[a * kSubLds + b]
-                                   : ((int32_t)jd.sub[a * alpha + b]) * (1 << K);
-      }
-    }
-  }
-  __syncthreads();
-
-  MSA_TRACE_POINT(jd, tile, 3);
-  // ---- sweep local hyperplanes ----
+    for (int r = 0; r < NR; ++r) dr[u][r] = 0;
   if (origin) {
     // every lane writes the same values (no lane-divergent branch)
     int s = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) s += C::sstride(i);
     sm.S[s] = 0;
-    sm.DIRB[0] = (uint8_t)M;  // decodes to mask 0
+    if constexpr (C::REGDIR)
+      dr[0][0] = tid == 0 ? (uint32_t)M : 0u;  // decodes to mask 0
+    else
+      sm.DIRB[0] = (uint8_t)M;
   } else {
+    constexpr int ML = C::ML;
+    constexpr int NPL = KL * (KL - 1) / 2;  // pairs within the line dimensions
     int hmax = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) hmax += ext[i] - 1;
+    const int extL = ext[KL];
     int32_t gk[K + 1];
 #pragma unroll
     for (int cb = 0; cb <= K; ++cb) gk[cb] = (gap * cb * (K - cb)) * (1 << K);
-    // Thread t takes the cells t, t + NT, ... of each hyperplane (at most U of
-    // them); the packed coordinates of hyperplane h + 1 are read from LDS while
-    // hyperplane h is computed, so one LDS round trip per hyperplane remains on
-    // the dependency chain.
-    constexpr int U = (C::MAXW + NT - 1) / NT;
-    constexpr uint32_t kNone = 0xFFFFu;
-    constexpr bool POW2 = (1 << C::B) == T;
-    uint32_t cur[U], nxt[U];
-    {
-      const int b0 = kHs<K>.v[0];
-      const int e0 = kHs<K>.v[1];
+
+    // Per lane and line: the word of cell (line, t = 0), the line's coordinate
+    // sum, and the pair-table rows of the pairs (i, k-1).  For k <= 4 the sums
+    // of the pair scores within the line dimensions (fixed along the line) are
+    // kept per neighbour mask b' over those dimensions; for larger k the pair
+    // scores are read from LDS at every step.
+    constexpr bool LREG = K <= 4;
+    int idx0[U], sq[U], pto[U][KL], qv[U][KL];
+    bool lv[U];
+    int32_t lsum[LREG ? U : 1][LREG ? ML + 1 : 1];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = b0 + tid + u * NT;
-        cur[u] = e < e0 ? (uint32_t)sm.CELLS[e] : kNone;
+    for (int u = 0; u < U; ++u) {
+      const int l = tid + u * NT;
+      int rem = l;
+#pragma unroll
+      for (int i = KL - 1; i >= 0; --i) {
+        qv[u][i] = rem % T;
+        rem /= T;
+      }
+      bool ok = l < L;
+      int s = 0, x = 1;
+#pragma unroll
+      for (int i = 0; i < KL; ++i) {
+        ok = ok && qv[u][i] < ext[i];
+        s += qv[u][i];
+        x += (qv[u][i] + 1) * C::sstride(i);
+        pto[u][i] = C::pair_index(i, KL) * T * T + qv[u][i] * T;
+      }
+      lv[u] = ok;
+      sq[u] = s;
+      idx0[u] = x;  // word of cell (line, t = 0)
+      if constexpr (LREG) {
+#pragma unroll
+        for (int bp = 0; bp <= ML; ++bp) {
+          int32_t cs = 0;
+#pragma unroll
+          for (int i = 0; i < KL; ++i)
+#pragma unroll
+            for (int j = i + 1; j < KL; ++j)
+              if (((bp >> i) & 1) && ((bp >> j) & 1))
+                cs += sm.PT[C::pair_index(i, j) * T * T + qv[u][i] * T + qv[u][j]];
+          lsum[u][bp] = cs;
+        }
       }
     }
-    for (int h = 0; h <= hmax; ++h) {
-      {
-        const int b1 = kHs<K>.v[h + 1];
-        const int e1 = kHs<K>.v[h + 2];
+    // prv[b'] = key of (line - b', t - 1); before the first step the t = -1
+    // layer is the halo.
+    int32_t prv[C::CARRY ? U : 1][C::CARRY ? ML + 1 : 1];
+    if constexpr (C::CARRY) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int e = b1 + tid + u * NT;
-          nxt[u] = e < e1 ? (uint32_t)sm.CELLS[e] : kNone;
-        }
-      }
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int bp = 0; bp <= ML; ++bp) prv[u][bp] = sm.S[idx0[u] - 1 - C::off(bp)];
+    }
+
+    for (int h = 0; h <= hmax; ++h) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const uint32_t pk = cur[u];
-        if (pk == kNone) continue;
-        int q[K];
-        bool ok = true;
+        const int t = h - sq[u];
+        if (!(lv[u] && (unsigned)t < (unsigned)extL)) continue;
+        const int p = idx0[u] + t;
+        int32_t pk[KL];
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-          q[i] = (pk >> ((K - 1 - i) * C::B)) & ((1u << C::B) - 1);
-          ok = ok && (full || q[i] < ext[i]);
+        for (int i = 0; i < KL; ++i) pk[i] = sm.PT[pto[u][i] + t];
+        int32_t pvl[LREG ? 1 : (NPL > 0 ? NPL : 1)];
+        if constexpr (!LREG) {
+          int pi = 0;
+#pragma unroll
+          for (int i = 0; i < KL; ++i)
+#pragma unroll
+            for (int j = i + 1; j < KL; ++j)
+              pvl[pi++] = sm.PT[C::pair_index(i, j) * T * T + qv[u][i] * T + qv[u][j]];
         }
-        if (!ok) continue;
-        int sidx = 0, didx = 0;
+        int32_t nowv[ML + 1];
+        if constexpr (C::CARRY) {
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-          sidx += (q[i] + 1) * C::sstride(i);
-          didx += q[i] * C::dstride(i);
+          for (int bp = 1; bp <= ML; ++bp) nowv[bp] = sm.S[p - C::off(bp)];
         }
-        if constexpr (POW2) didx = (int)pk;  // packed coordinates == block index
-        int32_t pv[C::NP > 0 ? C::NP : 1];
-#pragma unroll
-        for (int i = 0; i < K; ++i)
-#pragma unroll
-          for (int j = i + 1; j < K; ++j) {
-            // adjacent dimensions: q_i * T + q_j is a bit field of pk
-            const int pidx = (POW2 && j == i + 1)
-                                 ? (int)((pk >> ((K - 1 - j) * C::B)) & ((1u << (2 * C::B)) - 1))
-                                 : q[i] * T + q[j];
-            pv[C::pair_index(i, j)] = sm.PT[C::pair_index(i, j) * T * T + pidx];
-          }
         int32_t best = INT32_MIN;
 #pragma unroll
         for (int b = 1; b <= M; ++b) {
-          int32_t cs = 0;
+          const int bp = b & ML;
+          const bool hasL = (b >> KL) & 1;
+          // column score of candidate b (Section 2: sum over the pairs of the
+          // column), gap term and tie-break bits; all pre-shifted by k
+          int32_t col = gk[__builtin_popcount(b)] + (M - b);
+          if constexpr (LREG) {
+            if (__builtin_popcount(bp) >= 2) col += lsum[u][bp];
+          } else {
+            int pi = 0;
 #pragma unroll
-          for (int i = 0; i < K; ++i)
+            for (int i = 0; i < KL; ++i)
 #pragma unroll
-            for (int j = i + 1; j < K; ++j)
-              if (((b >> i) & 1) && ((b >> j) & 1)) cs += pv[C::pair_index(i, j)];
-          const int nb = __builtin_popcount(b);
-          const int32_t cand = sm.S[sidx - C::off(b)] + cs + gk[nb] + (M - b);
-          best = max(best, cand);
+              for (int j = i + 1; j < KL; ++j) {
+                if (((bp >> i) & 1) && ((bp >> j) & 1)) col += pvl[pi];
+                ++pi;
+              }
+          }
+          if (hasL) {
+#pragma unroll
+            for (int i = 0; i < KL; ++i)
+              if ((bp >> i) & 1) col += pk[i];
+          }
+          int32_t pred;
+          if constexpr (C::CARRY)
+            pred = hasL ? prv[u][bp] : nowv[bp];
+          else
+            pred = sm.S[p - C::off(b)];
+          best = max(best, pred + col);
+          // large k: at most 32 neighbour reads in flight (register pressure)
+          if constexpr (M > 63)
+            if ((b & 31) == 31) asm volatile("" ::: "memory");
         }
-        sm.S[sidx] = best & ~M;
-        sm.DIRB[didx] = (uint8_t)best;
+        const int32_t sv = best & ~M;
+        sm.S[p] = sv;
+        if constexpr (C::CARRY) {
+          prv[u][0] = sv;
+#pragma unroll
+          for (int bp = 1; bp <= ML; ++bp) prv[u][bp] = nowv[bp];
+        }
+        if constexpr (C::REGDIR)
+          shift_in<NR>(dr[u], (uint32_t)best & 0xFFu);
+        else
+          sm.DIRB[(tid + u * NT) * T + t] = (uint8_t)best;
       }
       __syncthreads();
+    }
+    if constexpr (C::REGDIR) {
+      // lines shorter than T: move byte t = 0 down to the first byte
+      for (int s = extL; s < T; ++s)
 #pragma unroll
-      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+        for (int u = 0; u < U; ++u) shift_in<NR>(dr[u], 0u);
     }
   }
   __syncthreads();
 
-  MSA_TRACE_POINT(jd, tile, 4);
+  MSA_TRACE_POINT(jd, tile, 3);
   if (corner) {  // all lanes store the same value
     int s = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) s += ext[i] * C::sstride(i);
     *jd.score_out = (int64_t)(sm.S[s] >> K);
+  }
+
+  // ---- direction block: cell (line, t) at byte line * T + t ----
+  {
+    uint8_t *blk = jd.dir + (int64_t)tile * C::DBS;
+    if constexpr (C::REGDIR) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int l = tid + u * NT;
+        if (l < L) {
+          if constexpr (NR % 4 == 0) {
+            uint4 *dst = reinterpret_cast<uint4 *>(blk + l * T);
+#pragma unroll
+            for (int r = 0; r < NR / 4; ++r)
+              dst[r] = make_uint4(dr[u][4 * r], dr[u][4 * r + 1], dr[u][4 * r + 2],
+                                  dr[u][4 * r + 3]);
+          } else if constexpr (NR == 2) {
+            *reinterpret_cast<uint2 *>(blk + l * T) = make_uint2(dr[u][0], dr[u][1]);
+          } else {
+            uint32_t *dst = reinterpret_cast<uint32_t *>(blk + l * T);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) dst[r] = dr[u][r];
+          }
+        }
+      }
+    } else {
+      const uint4 *src = reinterpret_cast<const uint4 *>(sm.DIRB);
+      uint4 *dst = reinterpret_cast<uint4 *>(blk);
+      for (int idx = tid; idx < C::DBS / 16; idx += NT) dst[idx] = src[idx];
+    }
   }
 
   // ---- export upper faces (layer l_i = ext_i) for the successor along i ----
@@ -467,13 +578,6 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
         for (int it = 0; it < IT; ++it)
           if (st[di][it]) face_store<SYNC>(jd.faces + fo[di][it], val[di][it]);
     }
-  }
-
-  // ---- export the direction block (16 bytes per lane) ----
-  {
-    uint4 *dst = reinterpret_cast<uint4 *>(jd.dir + (int64_t)tile * C::DBS);
-    const uint4 *src = reinterpret_cast<const uint4 *>(sm.DIRB);
-    for (int idx = tid; idx < C::DBS / 16; idx += NT) dst[idx] = src[idx];
   }
 
   MSA_TRACE_POINT(jd, tile, 5);
