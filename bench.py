@@ -168,6 +168,26 @@ def bench_served(n_jobs=20000, load=0.7, max_inflight=4, max_jobs=256):
             "max_inflight_launches": max_inflight, "max_jobs_per_launch": max_jobs}
 
 
+def measured_traffic():
+    """HBM bytes per launch of the k=3 fill from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a device copy), or
+    None when the kernel or launch sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "fill_k3_prot512_hbm_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in ("msa_kernels.hip", "msa_runtime.cpp"):
+        with open(os.path.join(ROOT, "paper_2311_17530_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    vals = dict(ln.split(": ", 1) for ln in text.splitlines() if ": " in ln and not ln.startswith(" "))
+    if vals.get("source_sha256 (msa_kernels.hip + msa_runtime.cpp)") != h.hexdigest():
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline():
     from msa_inputs import workload
     from oracle import build_oracle_lib, oracle_align
@@ -246,8 +266,8 @@ def main():
         "traceback_ms": round(main_r["traceback_ms_avg"], 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_INT32_TOPS, 2), "unit": "Tops/s",
-                     "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
-                     "kernel": "fill_kernel<3,256,2> (k=3, T=16, four waves per tile)",
+                     "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": measured_traffic(),
+                     "kernel": "fill_kernel<3,256,2> (k=3, T=16, one line per lane)",
                      "ops_per_launch": 2 * main_r["neighbour_updates"]},
         "extra": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                       for kk, vv in v.items()} for k, v in extra.items()},

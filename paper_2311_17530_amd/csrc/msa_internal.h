@@ -38,8 +38,6 @@ struct JobDev {
   // device pointers (filled per call for the plain path)
   const uint8_t *seqs;         // concatenated sequences
   const int8_t *sub;           // alpha x alpha
-  const uint32_t *cells;       // per-(k,T) hyperplane-sorted cell table
-  const int32_t *hstart;       // hyperplane starts into `cells`, H + 1 entries
   int32_t *faces;              // face planes (int32 keys)
   uint8_t *dir;                // tile-major direction blocks
   int32_t *flags;              // per-tile completion epoch

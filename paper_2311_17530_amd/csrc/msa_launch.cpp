@@ -139,17 +139,6 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   // ---- layout: [inputs (one host-to-device copy)][outputs][device only] ----
   int64_t o = 0;
   const int64_t off_ctrl = o;  o += 256;
-  int64_t off_cells[kMaxK + 1] = {}, off_hs[kMaxK + 1] = {};
-  bool need_k[kMaxK + 1] = {};
-  for (int i = 0; i < nj; ++i) need_k[jobs[i]->k] = true;
-  std::vector<std::vector<uint32_t>> cells(kMaxK + 1);
-  std::vector<std::vector<int32_t>> hs(kMaxK + 1);
-  for (int k = 2; k <= kMaxK; ++k) {
-    if (!need_k[k]) continue;
-    make_cell_table(k, tile_edge_for_k(k), &cells[k], &hs[k]);
-    off_cells[k] = o; o = a256(o + (int64_t)cells[k].size() * 4);
-    off_hs[k] = o;    o = a256(o + (int64_t)hs[k].size() * 4);
-  }
   const int64_t off_jobs = o;  o = a256(o + (int64_t)nj * sizeof(JobDev));
   const int64_t off_jt = o;    o = a256(o + (int64_t)(nj + 1) * 8);
   // substitution matrices, deduplicated by content
@@ -203,11 +192,6 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   memset(&ctrl, 0, sizeof(ctrl));
   ctrl.epoch = 1;
   memcpy(h + off_ctrl, &ctrl, sizeof(ctrl));
-  for (int k = 2; k <= kMaxK; ++k) {
-    if (!need_k[k]) continue;
-    memcpy(h + off_cells[k], cells[k].data(), cells[k].size() * 4);
-    memcpy(h + off_hs[k], hs[k].data(), hs[k].size() * 4);
-  }
   for (auto &kv : subs)
     memcpy(h + kv.second, kv.first.data(), kv.first.size() - 1);
   int64_t *jt = reinterpret_cast<int64_t *>(h + off_jt);
@@ -251,8 +235,6 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
     // device pointers
     jd.seqs = reinterpret_cast<const uint8_t *>(d_ + o_seq);
     jd.sub = reinterpret_cast<const int8_t *>(d_ + sub_off[i]);
-    jd.cells = reinterpret_cast<const uint32_t *>(d_ + off_cells[j.k]);
-    jd.hstart = reinterpret_cast<const int32_t *>(d_ + off_hs[j.k]);
     jd.wcnt = reinterpret_cast<const int32_t *>(d_ + o_wcnt);
     jd.wstart = reinterpret_cast<const int32_t *>(d_ + o_wst);
     jd.jstatus = reinterpret_cast<int32_t *>(d_ + o_jst);

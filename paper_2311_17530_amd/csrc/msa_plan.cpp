@@ -40,9 +40,25 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
   }
   q.nwaves = 1 - k;
   for (int i = 0; i < k; ++i) q.nwaves += q.P[i];
+  // tiles per wave: coefficients of prod_i (1 + x + ... + x^(P_i - 1))
+  {
+    std::vector<int64_t> cnt(q.nwaves + 1, 0), nxt(q.nwaves + 1, 0);
+    cnt[0] = 1;
+    int top = 0;
+    for (int i = 0; i < k; ++i) {
+      std::fill(nxt.begin(), nxt.end(), 0);
+      int64_t run = 0;  // sliding window sum of cnt[w - P_i + 1 .. w]
+      for (int w = 0; w <= top + q.P[i] - 1; ++w) {
+        if (w <= top) run += cnt[w];
+        if (w - q.P[i] >= 0) run -= cnt[w - q.P[i]];
+        nxt[w] = run;
+      }
+      top += q.P[i] - 1;
+      std::swap(cnt, nxt);
+    }
+    q.max_wave = *std::max_element(cnt.begin(), cnt.end());
+  }
   const int64_t nc = ipow(q.T, k);
-  q.ncells_table = (int32_t)nc;
-  q.H = k * (q.T - 1) + 1;
   q.dbs = (int32_t)((nc + 15) / 16 * 16);
   // face planes: dimension i keeps P_i - 1 planes over the other dimensions
   q.face_elems = 0;
@@ -63,8 +79,6 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
   int64_t o = 0;
   q.off_ctrl = o;   o = align256(o + (int64_t)sizeof(Ctrl));
   q.off_sub = o;    o = align256(o + kSubBytes);
-  q.off_cells = o;  o = align256(o + nc * 4);
-  q.off_hstart = o; o = align256(o + (int64_t)(q.H + 1) * 4);
   q.off_order = o;  o = align256(o + q.ntiles * 4);
   q.off_flags = o;  o = align256(o + q.ntiles * 4);
   q.off_path = o;   o = align256(o + std::max<int64_t>(q.total_len, 1));
@@ -78,40 +92,6 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
   q.bytes = o;
   *p = q;
   return MSA_OK;
-}
-
-void make_cell_table(int k, int T, std::vector<uint32_t> *cells, std::vector<int32_t> *hstart) {
-  const int B = bits_for(T - 1);
-  const int64_t nc = ipow(T, k);
-  const int H = k * (T - 1) + 1;
-  std::vector<int32_t> count(H + 1, 0);
-  std::vector<int32_t> hs(H + 1, 0);
-  auto hsum = [&](int64_t lin) {
-    int s = 0;
-    for (int i = k - 1; i >= 0; --i) {
-      s += (int)(lin % T);
-      lin /= T;
-    }
-    return s;
-  };
-  for (int64_t lin = 0; lin < nc; ++lin) count[hsum(lin)]++;
-  hs[0] = 0;
-  for (int h = 0; h < H; ++h) hs[h + 1] = hs[h] + count[h];
-  std::vector<int32_t> fillpos(hs.begin(), hs.end());
-  cells->assign(nc, 0);
-  for (int64_t lin = 0; lin < nc; ++lin) {
-    int64_t rem = lin;
-    uint32_t pk = 0;
-    int s = 0;
-    for (int i = k - 1; i >= 0; --i) {
-      const int q = (int)(rem % T);
-      rem /= T;
-      pk |= (uint32_t)q << ((k - 1 - i) * B);  // last dimension in the low bits
-      s += q;
-    }
-    (*cells)[fillpos[s]++] = pk;
-  }
-  *hstart = hs;
 }
 
 void make_tile_order(const Plan &p, std::vector<int32_t> *order) {
@@ -198,8 +178,6 @@ void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd) {
   jd->dbs = p.dbs;
   jd->total_len = p.total_len;
   jd->sub = reinterpret_cast<const int8_t *>(ws + p.off_sub);
-  jd->cells = reinterpret_cast<const uint32_t *>(ws + p.off_cells);
-  jd->hstart = reinterpret_cast<const int32_t *>(ws + p.off_hstart);
   jd->faces = reinterpret_cast<int32_t *>(ws + p.off_faces);
   jd->dir = reinterpret_cast<uint8_t *>(ws + p.off_dir);
   jd->flags = reinterpret_cast<int32_t *>(ws + p.off_flags);

@@ -26,10 +26,9 @@ struct Plan {
   int64_t fstride[kMaxK][kMaxK] = {};
   int64_t face_elems = 0;
   // workspace layout (byte offsets from the workspace base)
-  int64_t off_ctrl = 0, off_sub = 0, off_cells = 0, off_hstart = 0, off_order = 0,
-          off_flags = 0, off_path = 0, off_faces = 0, off_dir = 0, bytes = 0;
-  int32_t ncells_table = 0;  // T^k
-  int32_t H = 0;             // hyperplanes of a full tile
+  int64_t off_ctrl = 0, off_sub = 0, off_order = 0, off_flags = 0, off_path = 0,
+          off_faces = 0, off_dir = 0, bytes = 0;
+  int64_t max_wave = 0;      // tiles in the widest computation wave
 };
 
 constexpr int64_t kSubBytes = 255 * 255;
@@ -37,9 +36,6 @@ constexpr int64_t kMaxTiles = (int64_t)1 << 30;
 
 // Fills geometry and layout; returns 0 or a negative status.
 int make_plan(const int32_t *lens, int32_t k, Plan *p);
-
-// Cell table (hyperplane-sorted packed coordinates) and hyperplane starts.
-void make_cell_table(int k, int T, std::vector<uint32_t> *cells, std::vector<int32_t> *hstart);
 
 // Tiles ordered by computation wave (sum of tile coordinates).
 void make_tile_order(const Plan &p, std::vector<int32_t> *order);

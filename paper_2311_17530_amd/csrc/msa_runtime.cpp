@@ -40,9 +40,7 @@ static int occupancy(int k) {
 
 int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, int gap,
                       hipStream_t s) {
-  std::vector<uint32_t> cells;
-  std::vector<int32_t> hstart, order;
-  make_cell_table(p.k, p.T, &cells, &hstart);
+  std::vector<int32_t> order;
   make_tile_order(p, &order);
   Ctrl ctrl;
   memset(&ctrl, 0, sizeof(ctrl));
@@ -53,10 +51,6 @@ int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, 
   ok = ok && hipMemcpyAsync(ws + p.off_ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, s) ==
                  hipSuccess;
   ok = ok && hipMemcpyAsync(ws + p.off_sub, submat, (size_t)alpha * alpha,
-                            hipMemcpyHostToDevice, s) == hipSuccess;
-  ok = ok && hipMemcpyAsync(ws + p.off_cells, cells.data(), cells.size() * 4,
-                            hipMemcpyHostToDevice, s) == hipSuccess;
-  ok = ok && hipMemcpyAsync(ws + p.off_hstart, hstart.data(), hstart.size() * 4,
                             hipMemcpyHostToDevice, s) == hipSuccess;
   ok = ok && hipMemcpyAsync(ws + p.off_order, order.data(), order.size() * 4,
                             hipMemcpyHostToDevice, s) == hipSuccess;
@@ -85,7 +79,14 @@ int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, 
 #ifdef MSA_TRACE
   jd.trace = g_trace_buf;
 #endif
-  int64_t grid = (int64_t)device_cu_count() * occupancy(p.k);
+  // Persistent workgroups: as many tiles as the widest wave holds, rounded
+  // down to whole compute units, at least one per unit and at most what
+  // fits.  Beyond the widest wave extra workgroups only wait, and tiles that
+  // share a compute unit slow each other's sweep, which is the critical path.
+  const int64_t cu = device_cu_count();
+  int64_t grid = p.max_wave / cu * cu;
+  if (grid < cu) grid = cu;
+  if (grid > cu * occupancy(p.k)) grid = cu * occupancy(p.k);
   if (grid > p.ntiles) grid = p.ntiles;
   if (grid < 1) grid = 1;
   Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
