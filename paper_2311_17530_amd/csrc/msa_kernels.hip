@@ -28,6 +28,9 @@ enum { ST_OK = 0, ST_EINVAL = -1, ST_EDEVICE = -4 };
 
 constexpr int kSubLds = 32;  // substitution matrices up to 32x32 live in LDS
 
+// 16-byte vector moved as one value (plain loads and stores, no memcpy)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // LDS word strides of the tile with halo, dimension k-1 last (stride 1).  Each
 // stride exceeds T times the sum of the strides after it, so every cell of the
 // (T+1)^k box has its own word.  Within that freedom they are chosen so that
@@ -640,70 +643,133 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int M = C::M;
+  constexpr int NQ = C::DBS / 16;        // 16-byte chunks per direction block
+  constexpr int CPL = (NQ + 63) / 64;    // chunks per lane
+  // Blocks of the lower neighbour tiles are prefetched into registers on
+  // entering a tile: all 2^k - 1 of them while that takes at most 128
+  // registers, else the k face neighbours (other exits load on demand).
+  constexpr bool ALLN = M * CPL * 4 <= 128;
+  constexpr int NPF = ALLN ? M : K;
   const int tid = threadIdx.x;
   const int NT = blockDim.x;
   int status = __builtin_amdgcn_readfirstlane(status_in);
-  int v[K];
+
+  int v[K], c[K], q[K];
   bool done = true;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     v[i] = jd.n[i];
     done = done && v[i] == 0;
   }
-  int64_t L = 0;
   if (status != ST_OK) done = true;
-  while (!done) {
-    int t = 0, q[K], d = 0;
+  int Li = 0;                      // path length so far (sum n_i < 2^31)
+  int rem = (int)jd.total_len;     // steps still allowed
+  int pbuf = 0;  // path bytes L & ~63 .. L - 1, one per lane, flushed every 64
+  u32x4 *const lds4 = reinterpret_cast<u32x4 *>(dirb);
+
+  u32x4 pf[NPF > 0 ? NPF : 1][CPL];
+  int64_t t = 0;
+  if (!done) {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      const int ci = v[i] == 0 ? 0 : (v[i] - 1) / T + 1;
-      const int loi = ci == 0 ? 0 : (ci - 1) * T + 1;
-      t += ci * jd.tstride[i];
-      q[i] = v[i] - loi;
+      c[i] = v[i] == 0 ? 0 : (v[i] - 1) / T + 1;
+      t += (int64_t)c[i] * jd.tstride[i];
+    }
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(jd.dir + t * C::DBS);
+    for (int idx = tid; idx < NQ; idx += 64) lds4[idx] = src[idx];
+  }
+  while (!done) {
+    // position in the current tile (already in LDS)
+    int d = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      q[i] = v[i] - (c[i] == 0 ? 0 : (c[i] - 1) * T + 1);
       d += q[i] * C::dstride(i);
     }
-    __syncthreads();
-    {
-      const uint4 *src = reinterpret_cast<const uint4 *>(jd.dir + (int64_t)t * C::DBS);
-      uint4 *dst = reinterpret_cast<uint4 *>(dirb);
-      for (int idx = tid; idx < C::DBS / 16; idx += NT) dst[idx] = src[idx];
+    // prefetch the neighbour blocks (an absent neighbour loads this tile)
+#pragma unroll
+    for (int s = 0; s < NPF; ++s) {
+      const int S = ALLN ? s + 1 : 1 << s;
+      int64_t tn = t;
+      bool ok = true;
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+        if ((S >> i) & 1) {
+          ok = ok && c[i] > 0;
+          tn -= jd.tstride[i];
+        }
+      const u32x4 *src = reinterpret_cast<const u32x4 *>(jd.dir + (ok ? tn : t) * C::DBS);
+#pragma unroll
+      for (int x = 0; x < CPL; ++x) {
+        const int idx = tid + x * 64;
+        pf[s][x] = src[idx < NQ ? idx : NQ - 1];
+      }
     }
     __syncthreads();
-    for (;;) {
+    bool leave = false;
+    while (!done && !leave) {
       // every lane walks the same path: keep the walk state wave-uniform
       const int byte = __builtin_amdgcn_readfirstlane(dirb[d]);
       const int b = M - (byte & M);
-      bool bad = b == 0 || L >= jd.total_len;
+      int vor = 0, qor = 0;
 #pragma unroll
-      for (int i = 0; i < K; ++i) bad = bad || (((b >> i) & 1) && v[i] == 0);
-      if (bad) {  // corrupt decision data: never step outside the tensor
+      for (int i = 0; i < K; ++i) {
+        const int bi = (b >> i) & 1;
+        v[i] -= bi;
+        q[i] -= bi;
+        d -= bi * C::dstride(i);
+        vor |= v[i];
+        qor |= q[i];
+      }
+      // corrupt decision data (mask 0, a step below v_i = 0, a path longer
+      // than sum n_i): stop, never step outside the tensor
+      if (b == 0 || vor < 0 || rem <= 0) {
         status = ST_EDEVICE;
         done = true;
         break;
       }
-      jd.path[L] = (uint8_t)b;  // every lane stores the same byte
-      ++L;
-      bool all0 = true, leave = false;
+      --rem;
+      pbuf = tid == (Li & 63) ? b : pbuf;
+      ++Li;
+      if ((Li & 63) == 0) jd.path[Li - 64 + tid] = (uint8_t)pbuf;
+      done = vor == 0;
+      leave = qor < 0;
+    }
+    if (done) break;
+    // enter the next tile: its block was prefetched unless the walk left
+    // through an edge or corner that is not in the prefetched set
+    int S = 0;
+    t = 0;
 #pragma unroll
-      for (int i = 0; i < K; ++i) {
-        if ((b >> i) & 1) {
-          v[i] -= 1;
-          q[i] -= 1;
-          d -= C::dstride(i);
+    for (int i = 0; i < K; ++i) {
+      const int ci = v[i] == 0 ? 0 : (v[i] - 1) / T + 1;
+      if (ci != c[i]) S |= 1 << i;
+      c[i] = ci;
+      t += (int64_t)ci * jd.tstride[i];
+    }
+    __syncthreads();
+    bool hit = false;
+#pragma unroll
+    for (int s = 0; s < NPF; ++s) {
+      const int Ss = ALLN ? s + 1 : 1 << s;
+      if (Ss == S) {
+#pragma unroll
+        for (int x = 0; x < CPL; ++x) {
+          const int idx = tid + x * 64;
+          if (idx < NQ) lds4[idx] = pf[s][x];
         }
-        all0 = all0 && v[i] == 0;
-        leave = leave || q[i] < 0;
+        hit = true;
       }
-      if (all0) {
-        done = true;
-        break;
-      }
-      if (leave) break;
+    }
+    if (!hit) {
+      const u32x4 *src = reinterpret_cast<const u32x4 *>(jd.dir + t * C::DBS);
+      for (int idx = tid; idx < NQ; idx += 64) lds4[idx] = src[idx];
     }
   }
+  if ((Li & 63) != 0 && tid < (Li & 63)) jd.path[(Li & ~63) + tid] = (uint8_t)pbuf;
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  if (status != ST_OK) L = 0;
+  const int64_t L = status != ST_OK ? 0 : Li;
 
   // expand masks (path[L-1] is the first column) into gapped rows
   int cnt[K];

@@ -86,6 +86,12 @@ int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, 
   const int64_t cu = device_cu_count();
   int64_t grid = p.max_wave / cu * cu;
   if (grid < cu) grid = cu;
+  // MSA_WG_PER_CU (tuning): a fixed number of workgroups per compute unit
+  static const int wg_env = [] {
+    const char *e = getenv("MSA_WG_PER_CU");
+    return e ? atoi(e) : 0;
+  }();
+  if (wg_env > 0) grid = cu * wg_env;
   if (grid > cu * occupancy(p.k)) grid = cu * occupancy(p.k);
   if (grid > p.ntiles) grid = p.ntiles;
   if (grid < 1) grid = 1;
