@@ -502,43 +502,6 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
   __syncthreads();
 
   MSA_TRACE_POINT(jd, tile, 3);
-  if (corner) {  // all lanes store the same value
-    int s = 0;
-#pragma unroll
-    for (int i = 0; i < K; ++i) s += ext[i] * C::sstride(i);
-    *jd.score_out = (int64_t)(sm.S[s] >> K);
-  }
-
-  // ---- direction block: cell (line, t) at byte line * T + t ----
-  {
-    uint8_t *blk = jd.dir + (int64_t)tile * C::DBS;
-    if constexpr (C::REGDIR) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int l = tid + u * NT;
-        if (l < L) {
-          if constexpr (NR % 4 == 0) {
-            uint4 *dst = reinterpret_cast<uint4 *>(blk + l * T);
-#pragma unroll
-            for (int r = 0; r < NR / 4; ++r)
-              dst[r] = make_uint4(dr[u][4 * r], dr[u][4 * r + 1], dr[u][4 * r + 2],
-                                  dr[u][4 * r + 3]);
-          } else if constexpr (NR == 2) {
-            *reinterpret_cast<uint2 *>(blk + l * T) = make_uint2(dr[u][0], dr[u][1]);
-          } else {
-            uint32_t *dst = reinterpret_cast<uint32_t *>(blk + l * T);
-#pragma unroll
-            for (int r = 0; r < NR; ++r) dst[r] = dr[u][r];
-          }
-        }
-      }
-    } else {
-      const uint4 *src = reinterpret_cast<const uint4 *>(sm.DIRB);
-      uint4 *dst = reinterpret_cast<uint4 *>(blk);
-      for (int idx = tid; idx < C::DBS / 16; idx += NT) dst[idx] = src[idx];
-    }
-  }
-
   // ---- export upper faces (layer l_i = ext_i) for the successor along i ----
   // All LDS reads of a pass first (unconditional, clamped index), then the
   // predicated global stores, so the reads are not serialised against them.
@@ -600,6 +563,46 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
   if (wave == 0)
     __hip_atomic_store(jd.flags + tile, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   MSA_TRACE_POINT(jd, tile, 6);
+  // The score and the direction block are stored after the flag: only the
+  // traceback, a later kernel, reads them, and the completion wait before the
+  // flag then covers the face stores alone.
+  if (corner) {  // all lanes store the same value
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) s += ext[i] * C::sstride(i);
+    *jd.score_out = (int64_t)(sm.S[s] >> K);
+  }
+
+  // ---- direction block: cell (line, t) at byte line * T + t ----
+  {
+    uint8_t *blk = jd.dir + (int64_t)tile * C::DBS;
+    if constexpr (C::REGDIR) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int l = tid + u * NT;
+        if (l < L) {
+          if constexpr (NR % 4 == 0) {
+            uint4 *dst = reinterpret_cast<uint4 *>(blk + l * T);
+#pragma unroll
+            for (int r = 0; r < NR / 4; ++r)
+              dst[r] = make_uint4(dr[u][4 * r], dr[u][4 * r + 1], dr[u][4 * r + 2],
+                                  dr[u][4 * r + 3]);
+          } else if constexpr (NR == 2) {
+            *reinterpret_cast<uint2 *>(blk + l * T) = make_uint2(dr[u][0], dr[u][1]);
+          } else {
+            uint32_t *dst = reinterpret_cast<uint32_t *>(blk + l * T);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) dst[r] = dr[u][r];
+          }
+        }
+      }
+    } else {
+      const uint4 *src = reinterpret_cast<const uint4 *>(sm.DIRB);
+      uint4 *dst = reinterpret_cast<uint4 *>(blk);
+      for (int idx = tid; idx < C::DBS / 16; idx += NT) dst[idx] = src[idx];
+    }
+  }
+
 #ifdef MSA_TRACE
   if (jd.trace) jd.trace[(int64_t)tile * 8 + 7] = blockIdx.x;
 #endif
