@@ -8,6 +8,8 @@ package never imports the GPU library.
   one decision byte per cell, traceback from the far corner), following Eq. 1
   of the paper generalised to 2^k - 1 neighbours (Section 2) with the
   sum-of-pairs column score of Section 5.2.
+  ``msa_oracle_align_egf`` is the end-gap-free reading of the traceback start
+  ("highest score on the bottom edges", Section 2).
 - ``brute.py``      enumeration of every alignment of tiny inputs, scored
   column by column; the exact optimum and the tie rule by definition.
 """
@@ -15,6 +17,7 @@ from .oracle import (  # noqa: F401
     GAP,
     build_oracle_lib,
     oracle_align,
+    oracle_align_egf,
     oracle_fill,
     oracle_lib_path,
 )

@@ -104,3 +104,37 @@ def brute_force_align(seqs, sub, gap):
             else:
                 rows[i].append(GAP)
     return best, rows, n, n_opt
+
+
+def brute_force_egf_score(seqs, sub, gap):
+    """Best end-gap-free score by enumeration, independent of any recurrence.
+
+    End-gap-free reading of the traceback start ("highest score on the bottom
+    edges", Section 2): an alignment may leave a prefix and a suffix of the
+    sequences unaligned for free.  The aligned part (the core) aligns the
+    substrings s_i[a_i:e_i] where the start a has some a_i = 0 (a prefix of
+    every sequence but at least one is skipped) and the end e >= a has some
+    e_j = n_j (a suffix of every sequence but at least one is skipped).  The
+    score is the best sum-of-pairs score of any core.  Returns
+    ``(best_score, n_cores)`` with n_cores the number of (a, e, alignment)
+    triples enumerated.
+    """
+    import itertools
+
+    k = len(seqs)
+    seqs = [list(map(int, s)) for s in seqs]
+    lens = [len(s) for s in seqs]
+    best = None
+    n = 0
+    for a in itertools.product(*[range(m + 1) for m in lens]):
+        if all(x > 0 for x in a):
+            continue
+        for e in itertools.product(*[range(a[i], lens[i] + 1) for i in range(k)]):
+            if all(e[i] < lens[i] for i in range(k)):
+                continue
+            parts = [s[a[i]:e[i]] for i, s in enumerate(seqs)]
+            for score, _ in enumerate_alignments(parts, sub, gap):
+                n += 1
+                if best is None or score > best:
+                    best = score
+    return best, n

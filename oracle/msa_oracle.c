@@ -188,3 +188,148 @@ int msa_oracle_align(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
   free(rev);
   return 0;
 }
+
+/* End-gap-free fill: cells with some v_i = 0 score 0 and carry no decision;
+ * every other cell takes the maximum over all 2^k - 1 neighbours (they all
+ * exist), lowest mask on ties. */
+static void fill_egf(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                     int32_t alpha, const int32_t *sub, int32_t gap, int64_t *xi,
+                     uint8_t *D) {
+  int64_t stride[MSA_ORACLE_MAX_K];
+  int64_t ncell = 1;
+  for (int i = k - 1; i >= 0; --i) {
+    stride[i] = ncell;
+    ncell *= (int64_t)lens[i] + 1;
+  }
+  int64_t v[MSA_ORACLE_MAX_K];
+  int col[MSA_ORACLE_MAX_K];
+  const int nmask = 1 << k;
+  for (int64_t lin = 0; lin < ncell; ++lin) {
+    int64_t rem = lin;
+    int on_lower = 0;
+    for (int i = 0; i < k; ++i) {
+      v[i] = rem / stride[i];
+      rem -= v[i] * stride[i];
+      if (v[i] == 0) on_lower = 1;
+    }
+    if (on_lower) { /* free unaligned prefixes */
+      xi[lin] = 0;
+      D[lin] = 0;
+      continue;
+    }
+    int64_t best = 0;
+    int bestb = 0;
+    for (int b = 1; b < nmask; ++b) {
+      int64_t pred = lin;
+      for (int i = 0; i < k; ++i)
+        if ((b >> i) & 1) pred -= stride[i];
+      build_column(k, v, b, seqs, col);
+      int64_t cand = xi[pred] + sp_score(k, col, alpha, sub, gap);
+      if (b == 1 || cand > best) {
+        best = cand;
+        bestb = b;
+      }
+    }
+    xi[lin] = best;
+    D[lin] = (uint8_t)bestb;
+  }
+}
+
+int msa_oracle_align_egf(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                         int32_t alpha, const int32_t *sub, int32_t gap,
+                         int64_t *score_out, uint8_t *dir_out, uint8_t *aln_out,
+                         int64_t aln_cap, int64_t *aln_len_out,
+                         int64_t *core_begin_out, int64_t *core_end_out) {
+  if (validate(k, lens, seqs, alpha, sub) != 0) return -1;
+  if (!score_out || !aln_out || !aln_len_out) return -1;
+  int64_t total = 0;
+  for (int i = 0; i < k; ++i) total += lens[i];
+  if (aln_cap < total) return -1;
+
+  int64_t stride[MSA_ORACLE_MAX_K];
+  int64_t ncell = 1;
+  for (int i = k - 1; i >= 0; --i) {
+    stride[i] = ncell;
+    ncell *= (int64_t)lens[i] + 1;
+  }
+  int64_t *xi = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+  uint8_t *D = dir_out ? dir_out : (uint8_t *)malloc((size_t)ncell);
+  uint8_t *rev = (uint8_t *)malloc((size_t)(total > 0 ? total : 1) * (size_t)k);
+  if (!xi || !D || !rev) {
+    free(xi);
+    if (!dir_out) free(D);
+    free(rev);
+    return -1;
+  }
+  fill_egf(k, lens, seqs, alpha, sub, gap, xi, D);
+
+  /* end cell: best score among cells with some v_i = n_i; ties -> largest
+   * row-major index (the scan is ascending, so >= keeps the last one) */
+  int64_t v[MSA_ORACLE_MAX_K];
+  int64_t end = -1, best = 0;
+  for (int64_t lin = 0; lin < ncell; ++lin) {
+    int64_t rem = lin;
+    int on_upper = 0;
+    for (int i = 0; i < k; ++i) {
+      v[i] = rem / stride[i];
+      rem -= v[i] * stride[i];
+      if (v[i] == lens[i]) on_upper = 1;
+    }
+    if (!on_upper) continue;
+    if (end < 0 || xi[lin] >= best) {
+      best = xi[lin];
+      end = lin;
+    }
+  }
+  int64_t e[MSA_ORACLE_MAX_K];
+  {
+    int64_t rem = end;
+    for (int i = 0; i < k; ++i) {
+      e[i] = rem / stride[i];
+      rem -= e[i] * stride[i];
+      v[i] = e[i];
+    }
+  }
+  /* walk back while every v_i >= 1 */
+  int64_t lin = end, W = 0;
+  for (;;) {
+    int on_lower = 0;
+    for (int i = 0; i < k; ++i)
+      if (v[i] == 0) on_lower = 1;
+    if (on_lower) break;
+    int b = D[lin];
+    for (int i = 0; i < k; ++i) {
+      if ((b >> i) & 1) {
+        rev[W * k + i] = seqs[i][v[i] - 1];
+        v[i] -= 1;
+        lin -= stride[i];
+      } else {
+        rev[W * k + i] = MSA_ORACLE_GAP;
+      }
+    }
+    ++W;
+  }
+  /* assemble: prefixes v_i (start cell), walked columns, suffixes from e_i */
+  int64_t L = 0;
+  for (int i = 0; i < k; ++i)
+    for (int64_t t = 0; t < v[i]; ++t, ++L)
+      for (int j = 0; j < k; ++j)
+        aln_out[j * aln_cap + L] = (j == i) ? seqs[i][t] : MSA_ORACLE_GAP;
+  const int64_t core_begin = L;
+  for (int64_t c = 0; c < W; ++c, ++L)
+    for (int j = 0; j < k; ++j) aln_out[j * aln_cap + L] = rev[(W - 1 - c) * k + j];
+  const int64_t core_end = L;
+  for (int i = 0; i < k; ++i)
+    for (int64_t t = e[i]; t < lens[i]; ++t, ++L)
+      for (int j = 0; j < k; ++j)
+        aln_out[j * aln_cap + L] = (j == i) ? seqs[i][t] : MSA_ORACLE_GAP;
+
+  *score_out = best;
+  *aln_len_out = L;
+  if (core_begin_out) *core_begin_out = core_begin;
+  if (core_end_out) *core_end_out = core_end;
+  free(xi);
+  if (!dir_out) free(D);
+  free(rev);
+  return 0;
+}

@@ -60,6 +60,31 @@ int msa_oracle_align(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
                      uint8_t *aln_out, int64_t aln_cap, int64_t *aln_len_out);
 
 /*
+ * End-gap-free variant.  The paper starts its traceback "from the highest score
+ * on the bottom edges" (Section 2); read for k sequences as:
+ *   - every cell with some v_i = 0 scores 0 and has no decision (dir 0): any
+ *     prefixes may be left unaligned for free;
+ *   - every other cell follows the same recurrence as msa_oracle_align (all of
+ *     its 2^k - 1 neighbours exist);
+ *   - the score is the maximum over the cells with some v_i = n_i (the rest of
+ *     every sequence is left unaligned for free); among equal maxima the cell
+ *     with the largest row-major index ends the alignment;
+ *   - the walk goes back from that cell until it reaches a cell with some
+ *     v_i = 0;
+ *   - output columns: the unaligned prefixes (sequence 0 first, one residue
+ *     per column), then the walked columns, then the unaligned suffixes
+ *     (sequence 0 first, one residue per column).
+ * core_begin_out / core_end_out (may be NULL) receive the column range of the
+ * walked part; the score is the sum-of-pairs score of those columns.
+ * Other arguments and the return value as msa_oracle_align.
+ */
+int msa_oracle_align_egf(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                         int32_t alpha, const int32_t *sub, int32_t gap,
+                         int64_t *score_out, uint8_t *dir_out,
+                         uint8_t *aln_out, int64_t aln_cap, int64_t *aln_len_out,
+                         int64_t *core_begin_out, int64_t *core_end_out);
+
+/*
  * Score every cell: writes the full int64 score tensor (prod(lens[i]+1)
  * entries, same layout as dir_out) without a traceback.  Returns 0 or -1.
  */

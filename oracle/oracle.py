@@ -55,6 +55,9 @@ def _load():
         ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
         ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.msa_oracle_align_egf.restype = ctypes.c_int
+    lib.msa_oracle_align_egf.argtypes = lib.msa_oracle_align.argtypes + [
+        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.msa_oracle_fill.restype = ctypes.c_int
     lib.msa_oracle_fill.argtypes = [
         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -102,6 +105,34 @@ def oracle_align(seqs, sub, gap: int, want_dir: bool = False):
         raise ValueError("oracle rejected the input")
     rows = aln[:, : alen.value].copy()
     return int(score.value), rows, dirt
+
+
+def oracle_align_egf(seqs, sub, gap: int, want_dir: bool = False):
+    """End-gap-free optimal alignment (see ``msa_oracle_align_egf``).
+
+    Returns ``(score, rows, dir, (core_begin, core_end))``; the score is the
+    sum-of-pairs score of ``rows[:, core_begin:core_end]``.
+    """
+    lib = _load()
+    seqs, k, lens, ptrs, sub, alpha = _marshal(seqs, sub)
+    total = int(sum(len(s) for s in seqs))
+    cap = max(total, 1)
+    aln = np.full((k, cap), GAP, dtype=np.uint8)
+    shape = tuple(len(s) + 1 for s in seqs)
+    dirt = np.zeros(shape, dtype=np.uint8) if want_dir else None
+    score = ctypes.c_int64(0)
+    alen = ctypes.c_int64(0)
+    cb = ctypes.c_int64(0)
+    ce = ctypes.c_int64(0)
+    rc = lib.msa_oracle_align_egf(
+        k, lens, ptrs, alpha, sub.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        int(gap), ctypes.byref(score),
+        dirt.ctypes.data if dirt is not None else None,
+        aln.ctypes.data, cap, ctypes.byref(alen), ctypes.byref(cb), ctypes.byref(ce))
+    if rc != 0:
+        raise ValueError("oracle rejected the input")
+    rows = aln[:, : alen.value].copy()
+    return int(score.value), rows, dirt, (int(cb.value), int(ce.value))
 
 
 def oracle_fill(seqs, sub, gap: int):

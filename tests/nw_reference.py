@@ -47,3 +47,16 @@ def needleman_wunsch(a, b, sub, g):
         else:
             ra.append(0xFF); rb.append(int(b[j - 1])); j -= 1
     return int(F[n, m]), [ra[::-1], rb[::-1]], T
+
+
+def semiglobal_nw_score(a, b, sub, g):
+    """Textbook overlap (semi-global) alignment score of two sequences: end
+    gaps are free, i.e. xi(i,0) = xi(0,j) = 0 and the result is the maximum
+    over the last row and the last column."""
+    n, m = len(a), len(b)
+    F = np.zeros((n + 1, m + 1), dtype=np.int64)
+    for i in range(1, n + 1):
+        for j in range(1, m + 1):
+            F[i, j] = max(F[i - 1, j] + g, F[i, j - 1] + g,
+                          F[i - 1, j - 1] + int(sub[a[i - 1]][b[j - 1]]))
+    return int(max(F[n, :].max(), F[:, m].max()))
