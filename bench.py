@@ -15,8 +15,8 @@ already resident in HBM.  Prints one JSON line:
   cpu_baseline the oracle (plain single-threaded C) timed on this host on the
                full k=3 / 512 alignment
 
-The same numbers for the k=4 / 128 workload (129^4 cells) are reported under
-"extra"; "batched" gives jobs/s of the 4096-job workload through the batched
+The same numbers for the k=4 / 128 workload (129^4 cells) and for the k=3
+workload in end-gap-free mode are reported under "extra"; "batched" gives jobs/s of the 4096-job workload through the batched
 persistent launches (beside sequential plain calls), "served" the saturated
 throughput and p50/p99 latency of a 20000-job Poisson stream through the
 server at 0.7 times that rate.  Only one GPU is used: --gpus above 1 is
@@ -41,13 +41,13 @@ MAIN = "prot_k3_512"
 EXTRA = ["prot_k4_128"]
 
 
-def time_workload(name, steps, warmup):
+def time_workload(name, steps, warmup, end_gaps_free=False):
     import torch
     import paper_2311_17530_amd as msa
     from msa_inputs import workload
 
     job = workload(name)
-    dev = msa.DeviceAligner(job.lens, job.sub, job.gap)
+    dev = msa.DeviceAligner(job.lens, job.sub, job.gap, end_gaps_free=end_gaps_free)
     dev.set_sequences(job.seqs)
     torch.cuda.synchronize()
     for _ in range(warmup):
@@ -74,7 +74,8 @@ def time_workload(name, steps, warmup):
     nu = job.neighbour_updates
     fill_avg = float(np.mean(fill_ms))
     return dict(
-        workload=name, k=job.k, lens=job.lens, cells=cells, neighbour_updates=nu,
+        workload=name + (" end-gap-free" if end_gaps_free else ""), k=job.k, lens=job.lens,
+        cells=cells, neighbour_updates=nu,
         ms_per_step=ms_per_step, fill_ms_avg=fill_avg, fill_ms_min=float(np.min(fill_ms)),
         traceback_ms_avg=float(np.mean(tb_ms)),
         gcups=cells / (ms_per_step / 1e3) / 1e9,
@@ -244,6 +245,9 @@ def main():
     if not a.no_extra:
         for name in EXTRA:
             extra[name] = time_workload(name, a.steps, a.warmup)
+        # the end-gap-free mode on the same workload (same fill, zero faces,
+        # far-face maximum, traceback to the first face)
+        extra[MAIN + "_end_gaps_free"] = time_workload(MAIN, a.steps, a.warmup, True)
     achieved = main_r["fill_tops"]
     line = {
         "metric": "GCUPS",

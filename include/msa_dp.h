@@ -57,6 +57,9 @@ enum {
   MSA_ESHUTDOWN = -6   /* server: handle is shutting down */
 };
 
+/* Alignment mode flags (the _ex entry points). */
+#define MSA_END_GAPS_FREE 1u /* end-gap-free alignment, see msa_dp_align_ex */
+
 /* Human-readable text for a status code (static storage). */
 const char *msa_strerror(int status);
 
@@ -74,6 +77,26 @@ int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
                  const int8_t *submat, int32_t alpha, int32_t gap,
                  int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
                  int64_t *aln_len_out);
+
+/* ------------------------------------------------------------------------
+ * msa_dp_align_ex: msa_dp_align with mode flags (flags = 0 is msa_dp_align).
+ *
+ * MSA_END_GAPS_FREE: end-gap-free alignment, the reading of the paper's
+ *   traceback start "from the highest score on the bottom edges" (Section 2)
+ *   for k sequences.  Cells with some v_i = 0 score 0 (unaligned prefixes are
+ *   free); the score is the maximum over the cells with some v_i = n_i
+ *   (unaligned suffixes are free), the largest row-major cell index on ties;
+ *   the walk goes back from that cell to the first cell with some v_i = 0.
+ *   Output columns: the unaligned prefixes (sequence 0 first, one residue per
+ *   column), the walked columns, the unaligned suffixes (sequence 0 first,
+ *   one residue per column); the score is the sum-of-pairs score of the
+ *   walked columns.  Requires prod(lens[i] + 1) <= 2^32 (else MSA_ERANGE).
+ * Other flag bits: MSA_EINVAL.  Errors otherwise as msa_dp_align.
+ * ---------------------------------------------------------------------- */
+int msa_dp_align_ex(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
+                    const int8_t *submat, int32_t alpha, int32_t gap, uint32_t flags,
+                    int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
+                    int64_t *aln_len_out);
 
 /* ------------------------------------------------------------------------
  * Plain path, device-resident buffers (the form the benchmark times).
@@ -108,6 +131,14 @@ int64_t msa_dp_workspace_bytes(const int32_t *lens, int32_t k);
 int msa_dp_prepare(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
                    int32_t k, const int8_t *submat, int32_t alpha,
                    int32_t gap, void *hip_stream);
+
+/* msa_dp_prepare with mode flags (see msa_dp_align_ex); the mode is kept in
+ * the workspace and applies to every later msa_dp_align_dev,
+ * msa_dp_fill_dev / msa_dp_traceback_dev on it.  flags = 0 is
+ * msa_dp_prepare. */
+int msa_dp_prepare_ex(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
+                      int32_t k, const int8_t *submat, int32_t alpha,
+                      int32_t gap, uint32_t flags, void *hip_stream);
 
 int msa_dp_align_dev(void *d_workspace, int64_t ws_bytes,
                      const uint8_t *d_seqs, const int32_t *lens, int32_t k,

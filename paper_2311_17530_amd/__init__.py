@@ -10,6 +10,7 @@ from ._lib import (  # noqa: F401
     MSA_EAGAIN,
     MSA_EDEVICE,
     MSA_EINVAL,
+    MSA_END_GAPS_FREE,
     MSA_ENOMEM,
     MSA_ERANGE,
     MSA_ESHUTDOWN,

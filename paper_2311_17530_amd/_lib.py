@@ -55,14 +55,21 @@ class MsaResult(ctypes.Structure):
                 ("aln_len", ctypes.c_int64)]
 
 
+MSA_END_GAPS_FREE = 1  # alignment mode flag (msa_dp_align_ex / msa_dp_prepare_ex)
+
 _SIGS = {
     "msa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "msa_dp_align": (ctypes.c_int, [ctypes.POINTER(c_vp), c_i32p, ctypes.c_int32, c_vp,
                                     ctypes.c_int32, ctypes.c_int32, c_i64p, c_vp,
                                     ctypes.c_int64, c_i64p]),
+    "msa_dp_align_ex": (ctypes.c_int, [ctypes.POINTER(c_vp), c_i32p, ctypes.c_int32, c_vp,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                                       c_i64p, c_vp, ctypes.c_int64, c_i64p]),
     "msa_dp_workspace_bytes": (ctypes.c_int64, [c_i32p, ctypes.c_int32]),
     "msa_dp_prepare": (ctypes.c_int, [c_vp, ctypes.c_int64, c_i32p, ctypes.c_int32, c_vp,
                                       ctypes.c_int32, ctypes.c_int32, c_vp]),
+    "msa_dp_prepare_ex": (ctypes.c_int, [c_vp, ctypes.c_int64, c_i32p, ctypes.c_int32, c_vp,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32, c_vp]),
     "msa_dp_align_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p, ctypes.c_int32,
                                         c_vp, c_vp, ctypes.c_int64, c_vp, c_vp, c_vp]),
     "msa_dp_fill_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p, ctypes.c_int32,
@@ -165,8 +172,9 @@ def workspace_bytes(lens) -> int:
 # ---------------------------------------------------------------------------
 # plain path, host buffers
 # ---------------------------------------------------------------------------
-def align(seqs, sub, gap):
-    """Optimal alignment through ``msa_dp_align`` (host buffers).
+def align(seqs, sub, gap, end_gaps_free: bool = False):
+    """Optimal alignment through ``msa_dp_align_ex`` (host buffers);
+    ``end_gaps_free`` selects MSA_END_GAPS_FREE.
 
     Returns ``(score, rows)`` with rows a (k, L) uint8 array (GAP for gaps)."""
     seqs = [np.ascontiguousarray(np.asarray(s, dtype=np.uint8)) for s in seqs]
@@ -176,10 +184,11 @@ def align(seqs, sub, gap):
     out = np.full((k, cap), GAP, dtype=np.uint8)
     ptrs = (c_vp * k)(*[s.ctypes.data if len(s) else None for s in seqs])
     score, alen = ctypes.c_int64(), ctypes.c_int64()
-    rc = lib().msa_dp_align(ptrs, _i32arr([len(s) for s in seqs]), k, sub.ctypes.data,
-                            sub.shape[0], int(gap), ctypes.byref(score), out.ctypes.data,
-                            cap, ctypes.byref(alen))
-    _check(rc, "msa_dp_align")
+    rc = lib().msa_dp_align_ex(ptrs, _i32arr([len(s) for s in seqs]), k, sub.ctypes.data,
+                               sub.shape[0], int(gap),
+                               MSA_END_GAPS_FREE if end_gaps_free else 0,
+                               ctypes.byref(score), out.ctypes.data, cap, ctypes.byref(alen))
+    _check(rc, "msa_dp_align_ex")
     return int(score.value), out[:, : alen.value].copy()
 
 
@@ -192,7 +201,7 @@ class DeviceAligner:
     Owns a torch-allocated workspace and output tensors on ``device``; ``run``
     enqueues one alignment on the current torch stream (asynchronous)."""
 
-    def __init__(self, lens, sub, gap, device="cuda"):
+    def __init__(self, lens, sub, gap, device="cuda", end_gaps_free: bool = False):
         import torch
         self.torch = torch
         self.lens = [int(x) for x in lens]
@@ -210,10 +219,11 @@ class DeviceAligner:
         self.d_score = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.d_len = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.d_status = torch.zeros(1, dtype=torch.int32, device=self.device)
-        rc = lib().msa_dp_prepare(self.ws_ptr, self.ws_bytes, _i32arr(self.lens), self.k,
-                                  self.sub.ctypes.data, self.sub.shape[0], self.gap,
-                                  self._stream())
-        _check(rc, "msa_dp_prepare")
+        rc = lib().msa_dp_prepare_ex(self.ws_ptr, self.ws_bytes, _i32arr(self.lens), self.k,
+                                     self.sub.ctypes.data, self.sub.shape[0], self.gap,
+                                     MSA_END_GAPS_FREE if end_gaps_free else 0,
+                                     self._stream())
+        _check(rc, "msa_dp_prepare_ex")
 
     def _stream(self):
         return self.torch.cuda.current_stream(self.device).cuda_stream

@@ -86,9 +86,17 @@ extern "C" int64_t msa_dp_workspace_bytes(const int32_t *lens, int32_t k) {
   return p.bytes;
 }
 
-extern "C" int msa_dp_prepare(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
-                              int32_t k, const int8_t *submat, int32_t alpha, int32_t gap,
-                              void *hip_stream) {
+// Mode flags: only MSA_END_GAPS_FREE is defined; its end-cell key holds the
+// row-major cell index in 32 bits.
+static int check_flags(const Plan &p, uint32_t flags) {
+  if (flags & ~(uint32_t)MSA_END_GAPS_FREE) return MSA_EINVAL;
+  if ((flags & MSA_END_GAPS_FREE) && p.ncell > ((int64_t)1 << 32)) return MSA_ERANGE;
+  return MSA_OK;
+}
+
+extern "C" int msa_dp_prepare_ex(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
+                                 int32_t k, const int8_t *submat, int32_t alpha, int32_t gap,
+                                 uint32_t flags, void *hip_stream) {
   int rc = validate_shape(lens, k);
   if (rc) return rc;
   if (!d_workspace || ((uintptr_t)d_workspace & 255)) return MSA_EINVAL;
@@ -97,8 +105,17 @@ extern "C" int msa_dp_prepare(void *d_workspace, int64_t ws_bytes, const int32_t
   Plan p;
   rc = make_plan(lens, k, &p);
   if (rc) return rc;
+  rc = check_flags(p, flags);
+  if (rc) return rc;
   if (ws_bytes < p.bytes) return MSA_EINVAL;
-  return prepare_workspace(p, (char *)d_workspace, submat, alpha, gap, (hipStream_t)hip_stream);
+  return prepare_workspace(p, (char *)d_workspace, submat, alpha, gap, (int32_t)flags,
+                           (hipStream_t)hip_stream);
+}
+
+extern "C" int msa_dp_prepare(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
+                              int32_t k, const int8_t *submat, int32_t alpha, int32_t gap,
+                              void *hip_stream) {
+  return msa_dp_prepare_ex(d_workspace, ws_bytes, lens, k, submat, alpha, gap, 0u, hip_stream);
 }
 
 extern "C" int msa_dp_align_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
@@ -175,6 +192,7 @@ struct HostCache {
   int64_t io_bytes = 0;
   // signature of the prepared workspace
   int32_t k = 0, lens[MSA_MAX_K] = {}, alpha = 0, gap = 0;
+  uint32_t flags = 0;
   std::vector<int8_t> sub;
   hipStream_t stream = nullptr;
   ~HostCache() {
@@ -184,15 +202,17 @@ struct HostCache {
 thread_local HostCache g_cache;
 }  // namespace
 
-extern "C" int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
-                            const int8_t *submat, int32_t alpha, int32_t gap,
-                            int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
-                            int64_t *aln_len_out) {
+extern "C" int msa_dp_align_ex(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
+                               const int8_t *submat, int32_t alpha, int32_t gap, uint32_t flags,
+                               int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
+                               int64_t *aln_len_out) {
   int rc = validate_shape(lens, k);
   if (rc) return rc;
   if (!seqs || !score_out || !aln_len_out) return MSA_EINVAL;
   Plan p;
   rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  rc = check_flags(p, flags);
   if (rc) return rc;
   if (aln_cap < p.total_len || (p.total_len > 0 && !aln_out)) return MSA_EINVAL;
   for (int i = 0; i < k; ++i)
@@ -234,12 +254,12 @@ extern "C" int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int
     }
     c.io_bytes = io_need;
   }
-  bool same = c.k == k && c.alpha == alpha && c.gap == gap &&
+  bool same = c.k == k && c.alpha == alpha && c.gap == gap && c.flags == flags &&
               (int64_t)c.sub.size() == (int64_t)alpha * alpha &&
               memcmp(c.sub.data(), submat, (size_t)alpha * alpha) == 0;
   for (int i = 0; same && i < k; ++i) same = c.lens[i] == lens[i];
   if (!same) {
-    rc = prepare_workspace(p, (char *)c.ws, submat, alpha, gap, c.stream);
+    rc = prepare_workspace(p, (char *)c.ws, submat, alpha, gap, (int32_t)flags, c.stream);
     if (rc) {
       c.k = 0;
       return rc;
@@ -247,6 +267,7 @@ extern "C" int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int
     c.k = k;
     c.alpha = alpha;
     c.gap = gap;
+    c.flags = flags;
     for (int i = 0; i < k; ++i) c.lens[i] = lens[i];
     c.sub.assign(submat, submat + (size_t)alpha * alpha);
   }
@@ -281,4 +302,12 @@ extern "C" int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int
   *score_out = misc[0];
   *aln_len_out = L;
   return MSA_OK;
+}
+
+extern "C" int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
+                            const int8_t *submat, int32_t alpha, int32_t gap,
+                            int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
+                            int64_t *aln_len_out) {
+  return msa_dp_align_ex(seqs, lens, k, submat, alpha, gap, 0u, score_out, aln_out, aln_cap,
+                         aln_len_out);
 }

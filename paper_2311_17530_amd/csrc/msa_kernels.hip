@@ -164,9 +164,13 @@ __device__ inline void shift_in(uint32_t (&d)[NR], uint32_t byte) {
 // ---------------------------------------------------------------------------
 // One tile of the fill.
 // ---------------------------------------------------------------------------
+// egf: end-gap-free mode (plain path): tiles with some c_i = 0 hold the cells
+// with some v_i = 0, which score 0 with no decision; tiles on a far face fold
+// their far-face cells into *best as (score << 32 | row-major cell index).
 template <int K, int NT, int SYNC>
 __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int epoch,
-                             Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm) {
+                             Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm, bool egf = false,
+                             int64_t *best_key = nullptr) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int E = C::E;
@@ -179,7 +183,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
   asm volatile("" : "+v"(tid));
 
   int c[K], lo[K], ext[K];
-  bool origin = true, corner = true;
+  bool origin = true, corner = true, lowtile = false, fartile = false;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     c[i] = (tile / jd.tstride[i]) % jd.P[i];
@@ -187,8 +191,11 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     ext[i] = c[i] == 0 ? 1 : min(T, jd.n[i] - (c[i] - 1) * T);
     origin = origin && c[i] == 0;
     corner = corner && c[i] == jd.P[i] - 1;
+    lowtile = lowtile || c[i] == 0;
+    fartile = fartile || c[i] == jd.P[i] - 1;
   }
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) >> 6;
+  const bool zero_tile = egf && lowtile;  // every cell scores 0, no decision
 
   MSA_TRACE_POINT(jd, tile, 0);
   // ---- residues of this tile (v = lo + q; sequence index v - 1) ----
@@ -478,6 +485,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
           if constexpr (M > 63)
             if ((b & 31) == 31) asm volatile("" ::: "memory");
         }
+        if (zero_tile) best = M;  // key 0; the byte decodes to mask 0
         const int32_t sv = best & ~M;
         sm.S[p] = sv;
         if constexpr (C::CARRY) {
@@ -500,6 +508,55 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     }
   }
   __syncthreads();
+
+  // ---- end-gap-free: best far-face cell of this tile ----
+  // Cell (line, t) is on the far face of dimension i when c_i is the last tile
+  // coordinate and q_i = ext_i - 1.  Key: score << 32 | row-major index (the
+  // index fits 32 bits, checked on the host); largest key wins.
+  if (egf && fartile) {
+    constexpr int L = C::L;
+    constexpr int U = (L + NT - 1) / NT;
+    int64_t cs[K];  // row-major strides of the (n_i + 1) tensor
+    {
+      int64_t acc = 1;
+#pragma unroll
+      for (int i = K - 1; i >= 0; --i) {
+        cs[i] = acc;
+        acc *= (int64_t)jd.n[i] + 1;
+      }
+    }
+    int64_t mykey = INT64_MIN;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int l = tid + u * NT;
+      int q[KL > 0 ? KL : 1];
+      int rem = l;
+#pragma unroll
+      for (int i = KL - 1; i >= 0; --i) {
+        q[i] = rem % T;
+        rem /= T;
+      }
+      bool ok = l < L, whole = false;  // whole: every cell of the line is far
+      int x = 1;
+      int64_t lin = 0;
+#pragma unroll
+      for (int i = 0; i < KL; ++i) {
+        ok = ok && q[i] < ext[i];
+        whole = whole || (c[i] == jd.P[i] - 1 && q[i] == ext[i] - 1);
+        x += (q[i] + 1) * C::sstride(i);
+        lin += (int64_t)(lo[i] + q[i]) * cs[i];
+      }
+      const bool lastL = c[KL] == jd.P[KL] - 1;
+      if (ok && (whole || lastL)) {
+        for (int t = whole ? 0 : ext[KL] - 1; t < ext[KL]; ++t) {
+          const int64_t key = ((int64_t)(sm.S[x + t] >> K) << 32) |
+                              (int64_t)(uint32_t)(lin + (int64_t)(lo[KL] + t) * cs[KL]);
+          mykey = key > mykey ? key : mykey;
+        }
+      }
+    }
+    if (mykey != INT64_MIN) atomicMax((long long *)best_key, (long long)mykey);
+  }
 
   MSA_TRACE_POINT(jd, tile, 3);
   // ---- export upper faces (layer l_i = ext_i) for the successor along i ----
@@ -615,6 +672,7 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
   __shared__ Smem<K> sm;
   const int alpha = ctrl->alpha;
   const int gap = ctrl->gap;
+  const bool egf = (__builtin_amdgcn_readfirstlane(ctrl->flags) & kEndGapsFree) != 0;
   load_tables<K, NT>(jd, alpha, sm);
   const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
@@ -634,15 +692,20 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
     __syncthreads();
     if (qi >= jd.ntiles) break;
     process_tile<K, NT, SYNC>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]), epoch,
-                              ctrl, &ctrl->status, sm);
+                              ctrl, &ctrl->status, sm, egf, &ctrl->best);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Traceback: one workgroup of one wave.
 // ---------------------------------------------------------------------------
+// egf: end-gap-free mode; best is the fill's far-face key (score << 32 |
+// row-major index of the end cell).  The walk then starts at that cell, stops
+// at the first cell with some v_i = 0, and the unaligned suffixes and prefixes
+// become one-residue columns (sequence 0 first in the output).
 template <int K>
-__device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb) {
+__device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb, bool egf = false,
+                              int64_t best = 0) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int M = C::M;
@@ -658,16 +721,39 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb) {
   int status = __builtin_amdgcn_readfirstlane(status_in);
 
   int v[K], c[K], q[K];
-  bool done = true;
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    v[i] = jd.n[i];
-    done = done && v[i] == 0;
-  }
-  if (status != ST_OK) done = true;
   int Li = 0;                      // path length so far (sum n_i < 2^31)
   int rem = (int)jd.total_len;     // steps still allowed
   int pbuf = 0;  // path bytes L & ~63 .. L - 1, one per lane, flushed every 64
+  auto emit = [&](int b) {
+    pbuf = tid == (Li & 63) ? b : pbuf;
+    ++Li;
+    if ((Li & 63) == 0) jd.path[Li - 64 + tid] = (uint8_t)pbuf;
+  };
+  bool done = true;
+  if (egf) {
+    // end cell from its row-major index; the suffixes after it are emitted
+    // first (the path is recorded end first): sequence k-1's, ..., sequence 0's
+    int64_t lin = (int64_t)(uint32_t)best;
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+      v[i] = (int)(lin % ((int64_t)jd.n[i] + 1));
+      lin /= (int64_t)jd.n[i] + 1;
+    }
+    bool anyz = false;
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+      for (int x = v[i]; x < jd.n[i]; ++x) emit(1 << i);
+      anyz = anyz || v[i] == 0;
+    }
+    done = anyz;
+  } else {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      v[i] = jd.n[i];
+      done = done && v[i] == 0;
+    }
+  }
+  if (status != ST_OK) done = true;
   u32x4 *const lds4 = reinterpret_cast<u32x4 *>(dirb);
 
   u32x4 pf[NPF > 0 ? NPF : 1][CPL];
@@ -715,6 +801,7 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb) {
       const int byte = __builtin_amdgcn_readfirstlane(dirb[d]);
       const int b = M - (byte & M);
       int vor = 0, qor = 0;
+      bool anyz = false;
 #pragma unroll
       for (int i = 0; i < K; ++i) {
         const int bi = (b >> i) & 1;
@@ -723,6 +810,7 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb) {
         d -= bi * C::dstride(i);
         vor |= v[i];
         qor |= q[i];
+        anyz = anyz || v[i] == 0;
       }
       // corrupt decision data (mask 0, a step below v_i = 0, a path longer
       // than sum n_i): stop, never step outside the tensor
@@ -732,10 +820,8 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb) {
         break;
       }
       --rem;
-      pbuf = tid == (Li & 63) ? b : pbuf;
-      ++Li;
-      if ((Li & 63) == 0) jd.path[Li - 64 + tid] = (uint8_t)pbuf;
-      done = vor == 0;
+      emit(b);
+      done = egf ? anyz : vor == 0;
       leave = qor < 0;
     }
     if (done) break;
@@ -769,6 +855,12 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb) {
       for (int idx = tid; idx < NQ; idx += 64) lds4[idx] = src[idx];
     }
   }
+  if (egf && status == ST_OK) {
+    // the unaligned prefixes before the start cell: sequence k-1's, ..., 0's
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i)
+      for (int x = 0; x < v[i]; ++x) emit(1 << i);
+  }
   if ((Li & 63) != 0 && tid < (Li & 63)) jd.path[(Li & ~63) + tid] = (uint8_t)pbuf;
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -800,20 +892,25 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb) {
   if (tid == 0) {
     *jd.aln_len_out = L;
     *jd.status_out = status;
-    if (status != ST_OK) *jd.score_out = 0;
+    if (status != ST_OK)
+      *jd.score_out = 0;
+    else if (egf)
+      *jd.score_out = best >> 32;
   }
 }
 
 template <int K>
 __global__ __launch_bounds__(64) void traceback_kernel(JobDev jd, Ctrl *ctrl) {
   __shared__ alignas(16) uint8_t dirb[Cfg<K>::DBS];
+  const bool egf = (ctrl->flags & kEndGapsFree) != 0;
   traceback_job<K>(jd, __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                   dirb);
+                   dirb, egf, __hip_atomic_load(&ctrl->best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   __syncthreads();
   if (threadIdx.x == 0) {
     // ready the control block for the next launch on this workspace
     ctrl->head = 0;
     ctrl->status = ST_OK;
+    ctrl->best = INT64_MIN;
     ctrl->epoch = ctrl->epoch + 1;
   }
 }

@@ -39,6 +39,7 @@ static int occupancy(int k) {
 }
 
 int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, int gap,
+                      int32_t flags,
                       hipStream_t s) {
   std::vector<int32_t> order;
   make_tile_order(p, &order);
@@ -47,6 +48,8 @@ int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, 
   ctrl.epoch = 1;
   ctrl.alpha = alpha;
   ctrl.gap = gap;
+  ctrl.flags = flags;
+  ctrl.best = INT64_MIN;
   bool ok = true;
   ok = ok && hipMemcpyAsync(ws + p.off_ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, s) ==
                  hipSuccess;

@@ -20,7 +20,7 @@ int batch_occupancy(int kclass);
 // runtime (msa_runtime.cpp)
 int device_cu_count();
 int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, int gap,
-                      hipStream_t s);
+                      int32_t flags, hipStream_t s);
 // which: 1 = fill only, 2 = traceback only, 3 = both
 int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, uint8_t *d_aln,
               int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,

@@ -122,3 +122,26 @@ def test_workspace_bytes_and_errors():
     with pytest.raises(msa.MsaError):
         msa.workspace_bytes([3, -1])
     assert msa.strerror(msa.MSA_ERANGE).startswith("score range")
+
+
+def test_mode_flags_rejected_before_device():
+    import ctypes
+    sub, gap = dna_scoring()
+    sub8 = np.ascontiguousarray(sub.astype(np.int8))
+    a = np.array([0, 1, 2], np.uint8)
+    seqs = [a, a]
+    ptrs = (ctypes.c_void_p * 2)(*[s.ctypes.data for s in seqs])
+    lens = (ctypes.c_int32 * 2)(3, 3)
+    out = np.zeros((2, 6), np.uint8)
+    score, alen = ctypes.c_int64(), ctypes.c_int64()
+    rc = msa.lib().msa_dp_align_ex(ptrs, lens, 2, sub8.ctypes.data, 4, gap, 2,
+                                   ctypes.byref(score), out.ctypes.data, 6, ctypes.byref(alen))
+    assert rc == msa.MSA_EINVAL  # undefined flag bit
+    # end-gap-free keys hold the cell index in 32 bits
+    big = [np.zeros(70000, np.uint8)] * 2
+    with pytest.raises(msa.MsaError) as e:
+        msa.align(big, sub, gap, end_gaps_free=True)
+    assert e.value.status == msa.MSA_ERANGE
+    ws = 256  # any aligned address: rejected before it is touched
+    rc = msa.lib().msa_dp_prepare_ex(ws, 1 << 40, lens, 2, sub8.ctypes.data, 4, gap, 4, None)
+    assert rc == msa.MSA_EINVAL
