@@ -9,7 +9,8 @@ package never imports the GPU library.
   of the paper generalised to 2^k - 1 neighbours (Section 2) with the
   sum-of-pairs column score of Section 5.2.
   ``msa_oracle_align_egf`` is the end-gap-free reading of the traceback start
-  ("highest score on the bottom edges", Section 2).
+  ("highest score on the bottom edges", Section 2); ``msa_oracle_coopt``
+  enumerates co-optimal alignments (Section 6).
 - ``brute.py``      enumeration of every alignment of tiny inputs, scored
   column by column; the exact optimum and the tie rule by definition.
 """
@@ -18,6 +19,7 @@ from .oracle import (  # noqa: F401
     build_oracle_lib,
     oracle_align,
     oracle_align_egf,
+    oracle_coopt,
     oracle_fill,
     oracle_lib_path,
 )

@@ -138,3 +138,28 @@ def brute_force_egf_score(seqs, sub, gap):
                 if best is None or score > best:
                     best = score
     return best, n
+
+
+def brute_force_optima(seqs, sub, gap):
+    """Every optimal alignment, in the enumeration order above (lexicographic
+    in the column masks read from the last column to the first).  Returns
+    ``(best_score, [rows, ...])`` with rows as k lists of codes (GAP for gaps).
+    """
+    all_ = list(enumerate_alignments(seqs, sub, gap))
+    best = max(s for s, _ in all_)
+    k = len(seqs)
+    out = []
+    for score, masks in all_:
+        if score != best:
+            continue
+        pos = [0] * k
+        rows = [[] for _ in range(k)]
+        for b in reversed(masks):
+            for i in range(k):
+                if (b >> i) & 1:
+                    rows[i].append(int(seqs[i][pos[i]]))
+                    pos[i] += 1
+                else:
+                    rows[i].append(GAP)
+        out.append(rows)
+    return best, out

@@ -333,3 +333,130 @@ int msa_oracle_align_egf(int32_t k, const int32_t *lens, const uint8_t *const *s
   free(rev);
   return 0;
 }
+
+/* Global fill that keeps, per cell, the set of maximising masks (bit b - 1
+ * for mask b); same recurrence and candidates as fill(). */
+static void fill_ties(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                      int32_t alpha, const int32_t *sub, int32_t gap, int64_t *xi,
+                      uint8_t *TS) {
+  int64_t stride[MSA_ORACLE_MAX_K];
+  int64_t ncell = 1;
+  for (int i = k - 1; i >= 0; --i) {
+    stride[i] = ncell;
+    ncell *= (int64_t)lens[i] + 1;
+  }
+  int64_t v[MSA_ORACLE_MAX_K];
+  int col[MSA_ORACLE_MAX_K];
+  int64_t cand[256];
+  int valid[256];
+  const int nmask = 1 << k;
+  for (int64_t lin = 0; lin < ncell; ++lin) {
+    int64_t rem = lin;
+    for (int i = 0; i < k; ++i) {
+      v[i] = rem / stride[i];
+      rem -= v[i] * stride[i];
+    }
+    if (lin == 0) {
+      xi[0] = 0;
+      TS[0] = 0;
+      continue;
+    }
+    int have = 0;
+    int64_t best = 0;
+    for (int b = 1; b < nmask; ++b) {
+      valid[b] = 1;
+      int64_t pred = lin;
+      for (int i = 0; i < k; ++i)
+        if ((b >> i) & 1) {
+          if (v[i] == 0) valid[b] = 0;
+          pred -= stride[i];
+        }
+      if (!valid[b]) continue;
+      build_column(k, v, b, seqs, col);
+      cand[b] = xi[pred] + sp_score(k, col, alpha, sub, gap);
+      if (!have || cand[b] > best) best = cand[b];
+      have = 1;
+    }
+    uint8_t t = 0;
+    for (int b = 1; b < nmask; ++b)
+      if (valid[b] && cand[b] == best) t |= (uint8_t)(1u << (b - 1));
+    xi[lin] = best;
+    TS[lin] = t;
+  }
+}
+
+int msa_oracle_coopt(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                     int32_t alpha, const int32_t *sub, int32_t gap, int32_t max_paths,
+                     int64_t *score_out, uint8_t *tie_out, uint8_t *aln_out,
+                     int64_t aln_cap, int64_t *aln_len_out, int32_t *npaths_out) {
+  if (validate(k, lens, seqs, alpha, sub) != 0 || k > 3 || max_paths < 1) return -1;
+  if (!score_out || !aln_out || !aln_len_out || !npaths_out) return -1;
+  int64_t total = 0;
+  for (int i = 0; i < k; ++i) total += lens[i];
+  if (aln_cap < total) return -1;
+  int64_t stride[MSA_ORACLE_MAX_K];
+  int64_t ncell = 1;
+  for (int i = k - 1; i >= 0; --i) {
+    stride[i] = ncell;
+    ncell *= (int64_t)lens[i] + 1;
+  }
+  int64_t *xi = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+  uint8_t *TS = tie_out ? tie_out : (uint8_t *)malloc((size_t)ncell);
+  int *path = (int *)malloc((size_t)(total + 1) * sizeof(int)); /* mask per depth */
+  if (!xi || !TS || !path) {
+    free(xi);
+    if (!tie_out) free(TS);
+    free(path);
+    return -1;
+  }
+  fill_ties(k, lens, seqs, alpha, sub, gap, xi, TS);
+
+  /* depth-first walk from the far corner: path[d] is the mask taken at depth
+   * d, from the cell reached after the first d steps */
+  int64_t lin = ncell - 1;
+  int64_t d = 0;
+  int32_t np = 0;
+  path[0] = 0; /* next mask to try is the lowest one above path[d] */
+  for (;;) {
+    if (lin == 0) { /* reached the origin: emit the alignment of path[0..d) */
+      uint8_t *blk = aln_out + (int64_t)np * k * aln_cap;
+      int64_t pos[MSA_ORACLE_MAX_K];
+      for (int i = 0; i < k; ++i) pos[i] = 0;
+      for (int64_t c = 0; c < d; ++c) { /* columns origin first */
+        const int b = path[d - 1 - c];
+        for (int i = 0; i < k; ++i)
+          blk[i * aln_cap + c] = ((b >> i) & 1) ? seqs[i][pos[i]++] : MSA_ORACLE_GAP;
+      }
+      aln_len_out[np] = d;
+      if (++np == max_paths) break;
+      /* back up one step and try the next tied mask there */
+      if (d == 0) break;
+      --d;
+      for (int i = 0; i < k; ++i)
+        if ((path[d] >> i) & 1) lin += stride[i];
+    }
+    /* next mask of T(cell) above path[d] */
+    const uint8_t t = TS[lin];
+    int b = path[d] + 1;
+    while (b < (1 << k) && !((t >> (b - 1)) & 1)) ++b;
+    if (b < (1 << k)) {
+      path[d] = b;
+      for (int i = 0; i < k; ++i)
+        if ((b >> i) & 1) lin -= stride[i];
+      ++d;
+      path[d] = 0;
+      continue;
+    }
+    /* no mask left here: back up */
+    if (d == 0) break;
+    --d;
+    for (int i = 0; i < k; ++i)
+      if ((path[d] >> i) & 1) lin += stride[i];
+  }
+  *score_out = xi[ncell - 1];
+  *npaths_out = np;
+  free(xi);
+  if (!tie_out) free(TS);
+  free(path);
+  return 0;
+}

@@ -85,6 +85,29 @@ int msa_oracle_align_egf(int32_t k, const int32_t *lens, const uint8_t *const *s
                          int64_t *core_begin_out, int64_t *core_end_out);
 
 /*
+ * Co-optimal alignments (the paper's remark that the approach can also return
+ * co-optimal alignments, Section 6): the same global fill, but every cell
+ * keeps its tie set T(v) = { b : candidate b reaches the maximum }.  Every
+ * walk from the far corner that only steps along tie-set masks reaches the
+ * origin with the optimal score, and every optimal alignment is such a walk.
+ * They are enumerated depth first, the masks of each cell tried in ascending
+ * order, so alignments come in lexicographic order of their column masks read
+ * from the last column to the first; the first one is msa_oracle_align's.
+ *   max_paths   : at most this many alignments are returned (>= 1)
+ *   aln_out     : max_paths blocks of k rows of aln_cap bytes
+ *   aln_len_out : max_paths column counts
+ *   npaths_out  : number returned; fewer than max_paths means these are all
+ *   tie_out     : optional (may be NULL); prod(lens[i] + 1) bytes, bit b - 1
+ *                 set when mask b is in T(v) (k <= 8 uses the low bits of one
+ *                 byte; k <= 3 only, larger k is rejected)
+ * Returns 0, or -1 on invalid input (k > 3 included) / allocation failure.
+ */
+int msa_oracle_coopt(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                     int32_t alpha, const int32_t *sub, int32_t gap, int32_t max_paths,
+                     int64_t *score_out, uint8_t *tie_out, uint8_t *aln_out,
+                     int64_t aln_cap, int64_t *aln_len_out, int32_t *npaths_out);
+
+/*
  * Score every cell: writes the full int64 score tensor (prod(lens[i]+1)
  * entries, same layout as dir_out) without a traceback.  Returns 0 or -1.
  */

@@ -58,6 +58,13 @@ def _load():
     lib.msa_oracle_align_egf.restype = ctypes.c_int
     lib.msa_oracle_align_egf.argtypes = lib.msa_oracle_align.argtypes + [
         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.msa_oracle_coopt.restype = ctypes.c_int
+    lib.msa_oracle_coopt.argtypes = [
+        ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+        ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+        ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32,
+        ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
     lib.msa_oracle_fill.restype = ctypes.c_int
     lib.msa_oracle_fill.argtypes = [
         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -133,6 +140,33 @@ def oracle_align_egf(seqs, sub, gap: int, want_dir: bool = False):
         raise ValueError("oracle rejected the input")
     rows = aln[:, : alen.value].copy()
     return int(score.value), rows, dirt, (int(cb.value), int(ce.value))
+
+
+def oracle_coopt(seqs, sub, gap: int, max_paths: int, want_ties: bool = False):
+    """Up to ``max_paths`` co-optimal alignments (see ``msa_oracle_coopt``).
+
+    Returns ``(score, [rows, ...], ties)``; fewer than ``max_paths`` alignments
+    means all of them.  ``ties`` (if requested) holds bit b - 1 for every
+    maximising mask b of each cell."""
+    lib = _load()
+    seqs, k, lens, ptrs, sub, alpha = _marshal(seqs, sub)
+    total = int(sum(len(s) for s in seqs))
+    cap = max(total, 1)
+    aln = np.full((max_paths, k, cap), GAP, dtype=np.uint8)
+    alen = np.zeros(max_paths, dtype=np.int64)
+    shape = tuple(len(s) + 1 for s in seqs)
+    ties = np.zeros(shape, dtype=np.uint8) if want_ties else None
+    score = ctypes.c_int64(0)
+    npaths = ctypes.c_int32(0)
+    rc = lib.msa_oracle_coopt(
+        k, lens, ptrs, alpha, sub.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        int(gap), int(max_paths), ctypes.byref(score),
+        ties.ctypes.data if ties is not None else None, aln.ctypes.data, cap,
+        alen.ctypes.data, ctypes.byref(npaths))
+    if rc != 0:
+        raise ValueError("oracle rejected the input")
+    rows = [aln[p, :, : alen[p]].copy() for p in range(npaths.value)]
+    return int(score.value), rows, ties
 
 
 def oracle_fill(seqs, sub, gap: int):
