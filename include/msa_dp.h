@@ -59,6 +59,7 @@ enum {
 
 /* Alignment mode flags (the _ex entry points). */
 #define MSA_END_GAPS_FREE 1u /* end-gap-free alignment, see msa_dp_align_ex */
+#define MSA_COOPTIMAL 2u     /* tie sets kept for msa_dp_align_coopt */
 
 /* Human-readable text for a status code (static storage). */
 const char *msa_strerror(int status);
@@ -81,9 +82,9 @@ int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
 /* ------------------------------------------------------------------------
  * msa_dp_align_ex: msa_dp_align with mode flags (flags = 0 is msa_dp_align).
  *
- * MSA_END_GAPS_FREE: end-gap-free alignment, the reading of the paper's
- *   traceback start "from the highest score on the bottom edges" (Section 2)
- *   for k sequences.  Cells with some v_i = 0 score 0 (unaligned prefixes are
+ * MSA_END_GAPS_FREE: end-gap-free alignment, the reading of Section 2's
+ *   traceback start (the best-scoring cell of the far boundary) for k
+ *   sequences.  Cells with some v_i = 0 score 0 (unaligned prefixes are
  *   free); the score is the maximum over the cells with some v_i = n_i
  *   (unaligned suffixes are free), the largest row-major cell index on ties;
  *   the walk goes back from that cell to the first cell with some v_i = 0.
@@ -91,12 +92,52 @@ int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
  *   column), the walked columns, the unaligned suffixes (sequence 0 first,
  *   one residue per column); the score is the sum-of-pairs score of the
  *   walked columns.  Requires prod(lens[i] + 1) <= 2^32 (else MSA_ERANGE).
+ * MSA_COOPTIMAL: the fill keeps every maximising mask of each cell (its tie
+ *   set, bit b - 1 for mask b); the alignment returned is the same as with
+ *   flags = 0.  Requires k <= 3 and sum(lens) <= 32768 (MSA_EINVAL /
+ *   MSA_ERANGE otherwise); not combinable with MSA_END_GAPS_FREE (MSA_EINVAL).
  * Other flag bits: MSA_EINVAL.  Errors otherwise as msa_dp_align.
  * ---------------------------------------------------------------------- */
 int msa_dp_align_ex(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
                     const int8_t *submat, int32_t alpha, int32_t gap, uint32_t flags,
                     int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
                     int64_t *aln_len_out);
+
+/* ------------------------------------------------------------------------
+ * msa_dp_align_coopt: up to max_paths co-optimal alignments (every global
+ * alignment with the optimal score): Section 6 proposes a traceback that
+ * branches wherever several choices tie.  Synchronous, host
+ * buffers, same device-memory cache as msa_dp_align.
+ *   max_paths   : >= 1
+ *   score_out   : the optimal score
+ *   aln_out     : max_paths blocks of k rows of aln_cap bytes; alignment p
+ *                 is at aln_out + p * k * aln_cap (layout as msa_dp_align)
+ *   aln_len_out : max_paths int64, the column count of each alignment
+ *   npaths_out  : number of alignments written; fewer than max_paths means
+ *                 every co-optimal alignment was written
+ * Order: the walk from the far corner tries the tied masks of each cell in
+ * ascending order, so alignment 0 is msa_dp_align's and the list is sorted
+ * by the column masks read from the last column to the first.
+ * Requires k <= 3 and sum(lens) <= 32768.  Errors as msa_dp_align, and
+ * MSA_EINVAL for k > 3 or max_paths < 1, MSA_ERANGE for longer inputs.
+ * ---------------------------------------------------------------------- */
+int msa_dp_align_coopt(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
+                       const int8_t *submat, int32_t alpha, int32_t gap, int32_t max_paths,
+                       int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
+                       int64_t *aln_len_out, int32_t *npaths_out);
+
+/* Device-buffer form of msa_dp_align_coopt on a workspace prepared with
+ * msa_dp_prepare_ex(..., MSA_COOPTIMAL, ...): enqueues the fill and the
+ * enumeration on hip_stream (asynchronous).  d_aln holds max_paths * k rows
+ * of aln_cap bytes, d_aln_len max_paths int64, d_npaths one int32; d_status
+ * as msa_dp_align_dev, and MSA_EINVAL when the workspace was not prepared
+ * with MSA_COOPTIMAL (d_npaths and d_score read 0 when it is not MSA_OK).
+ * Returns MSA_EINVAL / MSA_ERANGE at once, enqueuing nothing, for k > 3,
+ * sum(lens) > 32768, max_paths < 1 or the errors of msa_dp_align_dev. */
+int msa_dp_coopt_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
+                     const int32_t *lens, int32_t k, int32_t max_paths, int64_t *d_score,
+                     uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len,
+                     int32_t *d_npaths, int32_t *d_status, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Plain path, device-resident buffers (the form the benchmark times).
@@ -160,8 +201,10 @@ int msa_dp_traceback_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_s
 
 /* Copy the decision tensor of the last alignment run on `d_workspace` into
  * d_dir_out: prod(lens[i] + 1) bytes, row-major with the last sequence's
- * index fastest, byte = chosen neighbour mask b (0 at the origin).  For
- * verification.  Asynchronous on hip_stream. */
+ * index fastest, byte = chosen neighbour mask b (0 at the origin); on a
+ * workspace prepared with MSA_COOPTIMAL, byte = the cell's tie set (bit b - 1
+ * for each maximising mask b, 0 at the origin).  For verification.
+ * Asynchronous on hip_stream. */
 int msa_dp_export_dirs(void *d_workspace, int64_t ws_bytes,
                        const int32_t *lens, int32_t k, uint8_t *d_dir_out,
                        void *hip_stream);

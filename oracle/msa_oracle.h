@@ -60,8 +60,8 @@ int msa_oracle_align(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
                      uint8_t *aln_out, int64_t aln_cap, int64_t *aln_len_out);
 
 /*
- * End-gap-free variant.  The paper starts its traceback "from the highest score
- * on the bottom edges" (Section 2); read for k sequences as:
+ * End-gap-free variant.  Section 2 starts the traceback at the best-scoring
+ * cell of the tensor's far boundary; read for k sequences as:
  *   - every cell with some v_i = 0 scores 0 and has no decision (dir 0): any
  *     prefixes may be left unaligned for free;
  *   - every other cell follows the same recurrence as msa_oracle_align (all of

@@ -7,6 +7,7 @@ The compute path is the HIP library ``_lib/libmsa_dp.so`` (C ABI in
 from ._lib import (  # noqa: F401
     GAP,
     MAX_K,
+    MSA_COOPTIMAL,
     MSA_EAGAIN,
     MSA_EDEVICE,
     MSA_EINVAL,
@@ -20,6 +21,7 @@ from ._lib import (  # noqa: F401
     Server,
     align,
     align_batch,
+    align_coopt,
     exported_names,
     lib,
     score_bounds,

@@ -55,7 +55,9 @@ class MsaResult(ctypes.Structure):
                 ("aln_len", ctypes.c_int64)]
 
 
-MSA_END_GAPS_FREE = 1  # alignment mode flag (msa_dp_align_ex / msa_dp_prepare_ex)
+# alignment mode flags (msa_dp_align_ex / msa_dp_prepare_ex)
+MSA_END_GAPS_FREE = 1
+MSA_COOPTIMAL = 2
 
 _SIGS = {
     "msa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -65,6 +67,9 @@ _SIGS = {
     "msa_dp_align_ex": (ctypes.c_int, [ctypes.POINTER(c_vp), c_i32p, ctypes.c_int32, c_vp,
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                        c_i64p, c_vp, ctypes.c_int64, c_i64p]),
+    "msa_dp_align_coopt": (ctypes.c_int, [ctypes.POINTER(c_vp), c_i32p, ctypes.c_int32, c_vp,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          c_i64p, c_vp, ctypes.c_int64, c_vp, c_i32p]),
     "msa_dp_workspace_bytes": (ctypes.c_int64, [c_i32p, ctypes.c_int32]),
     "msa_dp_prepare": (ctypes.c_int, [c_vp, ctypes.c_int64, c_i32p, ctypes.c_int32, c_vp,
                                       ctypes.c_int32, ctypes.c_int32, c_vp]),
@@ -79,6 +84,9 @@ _SIGS = {
                                             c_vp, c_vp]),
     "msa_dp_export_dirs": (ctypes.c_int, [c_vp, ctypes.c_int64, c_i32p, ctypes.c_int32,
                                           c_vp, c_vp]),
+    "msa_dp_coopt_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p, ctypes.c_int32,
+                                        ctypes.c_int32, c_vp, c_vp, ctypes.c_int64, c_vp,
+                                        c_vp, c_vp, c_vp]),
     "msa_dp_align_batch": (ctypes.c_int, [ctypes.POINTER(MsaJob), ctypes.c_int32,
                                           ctypes.POINTER(MsaResult), ctypes.c_int64]),
     "msa_server_create": (c_vp, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
@@ -192,6 +200,27 @@ def align(seqs, sub, gap, end_gaps_free: bool = False):
     return int(score.value), out[:, : alen.value].copy()
 
 
+def align_coopt(seqs, sub, gap, max_paths: int):
+    """Up to ``max_paths`` co-optimal alignments through ``msa_dp_align_coopt``.
+
+    Returns ``(score, [rows, ...])``; fewer than ``max_paths`` alignments means
+    all of them (alignment 0 is ``align``'s)."""
+    seqs = [np.ascontiguousarray(np.asarray(s, dtype=np.uint8)) for s in seqs]
+    sub = np.ascontiguousarray(np.asarray(sub, dtype=np.int8))
+    k = len(seqs)
+    cap = max(1, sum(len(s) for s in seqs))
+    out = np.full((int(max_paths), k, cap), GAP, dtype=np.uint8)
+    lens_out = np.zeros(max(1, int(max_paths)), dtype=np.int64)
+    ptrs = (c_vp * k)(*[s.ctypes.data if len(s) else None for s in seqs])
+    score, npaths = ctypes.c_int64(), ctypes.c_int32()
+    rc = lib().msa_dp_align_coopt(ptrs, _i32arr([len(s) for s in seqs]), k, sub.ctypes.data,
+                                  sub.shape[0], int(gap), int(max_paths), ctypes.byref(score),
+                                  out.ctypes.data, cap, lens_out.ctypes.data,
+                                  ctypes.byref(npaths))
+    _check(rc, "msa_dp_align_coopt")
+    return int(score.value), [out[p, :, : lens_out[p]].copy() for p in range(npaths.value)]
+
+
 # ---------------------------------------------------------------------------
 # plain path, device buffers (torch provides memory and the stream)
 # ---------------------------------------------------------------------------
@@ -201,7 +230,8 @@ class DeviceAligner:
     Owns a torch-allocated workspace and output tensors on ``device``; ``run``
     enqueues one alignment on the current torch stream (asynchronous)."""
 
-    def __init__(self, lens, sub, gap, device="cuda", end_gaps_free: bool = False):
+    def __init__(self, lens, sub, gap, device="cuda", end_gaps_free: bool = False,
+                 cooptimal: bool = False):
         import torch
         self.torch = torch
         self.lens = [int(x) for x in lens]
@@ -219,10 +249,11 @@ class DeviceAligner:
         self.d_score = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.d_len = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.d_status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        flags = (MSA_END_GAPS_FREE if end_gaps_free else 0) | (
+            MSA_COOPTIMAL if cooptimal else 0)
         rc = lib().msa_dp_prepare_ex(self.ws_ptr, self.ws_bytes, _i32arr(self.lens), self.k,
                                      self.sub.ctypes.data, self.sub.shape[0], self.gap,
-                                     MSA_END_GAPS_FREE if end_gaps_free else 0,
-                                     self._stream())
+                                     flags, self._stream())
         _check(rc, "msa_dp_prepare_ex")
 
     def _stream(self):
@@ -255,6 +286,35 @@ class DeviceAligner:
                                         self.d_status.data_ptr(), self._stream())
         _check(rc, "msa_dp_traceback_dev")
 
+    def run_coopt(self, max_paths: int):
+        """Enqueue the fill and the enumeration of up to ``max_paths``
+        co-optimal alignments (``msa_dp_coopt_dev``); read them with
+        ``result_coopt``."""
+        if getattr(self, "_co_max", 0) != max_paths:
+            t = self.torch
+            self._co_max = int(max_paths)
+            self.d_co_aln = t.full((self._co_max, self.k, self.cap), GAP, dtype=t.uint8,
+                                   device=self.device)
+            self.d_co_len = t.zeros(max(1, self._co_max), dtype=t.int64, device=self.device)
+            self.d_co_np = t.zeros(1, dtype=t.int32, device=self.device)
+        rc = lib().msa_dp_coopt_dev(self.ws_ptr, self.ws_bytes, self.d_seqs.data_ptr(),
+                                    _i32arr(self.lens), self.k, int(max_paths),
+                                    self.d_score.data_ptr(), self.d_co_aln.data_ptr(), self.cap,
+                                    self.d_co_len.data_ptr(), self.d_co_np.data_ptr(),
+                                    self.d_status.data_ptr(), self._stream())
+        _check(rc, "msa_dp_coopt_dev")
+
+    def result_coopt(self):
+        """Synchronise and return ``(score, [rows, ...])`` of ``run_coopt``."""
+        self.torch.cuda.current_stream(self.device).synchronize()
+        st = int(self.d_status.item())
+        if st != MSA_OK:
+            raise MsaError(st, "device status")
+        n = int(self.d_co_np.item())
+        lens = self.d_co_len[:n].cpu().numpy()
+        aln = self.d_co_aln[:n].cpu().numpy()
+        return int(self.d_score.item()), [aln[p, :, : lens[p]].copy() for p in range(n)]
+
     def result(self):
         """Synchronise and return ``(score, rows)`` (raises on device status)."""
         self.torch.cuda.current_stream(self.device).synchronize()
@@ -266,7 +326,9 @@ class DeviceAligner:
         return int(self.d_score.item()), rows
 
     def export_dirs(self):
-        """Row-major decision tensor (neighbour mask per cell) of the last run."""
+        """Row-major decision tensor of the last run: the neighbour mask per
+        cell, or the tie set per cell (bit b - 1 for mask b) when the aligner
+        was made with ``cooptimal``."""
         shape = tuple(n + 1 for n in self.lens)
         out = self.torch.empty(int(np.prod(shape)), dtype=self.torch.uint8, device=self.device)
         rc = lib().msa_dp_export_dirs(self.ws_ptr, self.ws_bytes, _i32arr(self.lens), self.k,

@@ -86,11 +86,17 @@ extern "C" int64_t msa_dp_workspace_bytes(const int32_t *lens, int32_t k) {
   return p.bytes;
 }
 
-// Mode flags: only MSA_END_GAPS_FREE is defined; its end-cell key holds the
-// row-major cell index in 32 bits.
+// Mode flags.  The end-gap-free end-cell key holds the row-major cell index
+// in 32 bits; a co-optimal tie set fits a byte for k <= 3 and its walk keeps
+// one mask per column on chip.
 static int check_flags(const Plan &p, uint32_t flags) {
-  if (flags & ~(uint32_t)MSA_END_GAPS_FREE) return MSA_EINVAL;
+  if (flags & ~(uint32_t)(MSA_END_GAPS_FREE | MSA_COOPTIMAL)) return MSA_EINVAL;
+  if ((flags & MSA_END_GAPS_FREE) && (flags & MSA_COOPTIMAL)) return MSA_EINVAL;
   if ((flags & MSA_END_GAPS_FREE) && p.ncell > ((int64_t)1 << 32)) return MSA_ERANGE;
+  if (flags & MSA_COOPTIMAL) {
+    if (p.k > kCoMaxK) return MSA_EINVAL;
+    if (p.total_len > kCoMaxTotal) return MSA_ERANGE;
+  }
   return MSA_OK;
 }
 
@@ -180,6 +186,27 @@ extern "C" int msa_dp_export_dirs(void *d_workspace, int64_t ws_bytes, const int
   return export_dirs(p, (char *)d_workspace, d_dir_out, (hipStream_t)hip_stream);
 }
 
+extern "C" int msa_dp_coopt_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
+                                const int32_t *lens, int32_t k, int32_t max_paths,
+                                int64_t *d_score, uint8_t *d_aln, int64_t aln_cap,
+                                int64_t *d_aln_len, int32_t *d_npaths, int32_t *d_status,
+                                void *hip_stream) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255) || !d_score || !d_aln_len || !d_npaths ||
+      !d_status || !d_aln || max_paths < 1)
+    return MSA_EINVAL;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  rc = check_flags(p, MSA_COOPTIMAL);
+  if (rc) return rc;
+  if (ws_bytes < p.bytes || aln_cap < p.total_len || (p.total_len > 0 && !d_seqs))
+    return MSA_EINVAL;
+  return run_coopt(p, (char *)d_workspace, d_seqs, max_paths, d_score, d_aln, aln_cap,
+                   d_aln_len, d_npaths, d_status, (hipStream_t)hip_stream);
+}
+
 // ---------------------------------------------------------------------------
 // Host-buffer convenience path: a per-thread cache of device buffers.
 // ---------------------------------------------------------------------------
@@ -202,25 +229,18 @@ struct HostCache {
 thread_local HostCache g_cache;
 }  // namespace
 
-extern "C" int msa_dp_align_ex(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
-                               const int8_t *submat, int32_t alpha, int32_t gap, uint32_t flags,
-                               int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
-                               int64_t *aln_len_out) {
-  int rc = validate_shape(lens, k);
-  if (rc) return rc;
-  if (!seqs || !score_out || !aln_len_out) return MSA_EINVAL;
-  Plan p;
-  rc = make_plan(lens, k, &p);
-  if (rc) return rc;
-  rc = check_flags(p, flags);
-  if (rc) return rc;
-  if (aln_cap < p.total_len || (p.total_len > 0 && !aln_out)) return MSA_EINVAL;
+// Validates a host-buffer call and readies the per-thread cache: a workspace
+// prepared for (lens, scoring, flags), `io_need` bytes of device I/O buffers,
+// and the sequences copied to the start of the I/O buffer (enqueued).
+static int host_call_setup(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
+                           const int8_t *submat, int32_t alpha, int32_t gap, uint32_t flags,
+                           const Plan &p, int64_t io_need) {
   for (int i = 0; i < k; ++i)
     if (lens[i] > 0 && !seqs[i]) return MSA_EINVAL;
   for (int i = 0; i < k; ++i)
     for (int32_t t = 0; t < lens[i]; ++t)
       if (seqs[i][t] >= alpha) return MSA_EINVAL;
-  rc = check_scoring(lens, k, submat, alpha, gap);
+  int rc = check_scoring(lens, k, submat, alpha, gap);
   if (rc) return rc;
 
   HostCache &c = g_cache;
@@ -232,7 +252,6 @@ extern "C" int msa_dp_align_ex(const uint8_t *const *seqs, const int32_t *lens, 
     if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess)
       return MSA_EDEVICE;
   }
-  const int64_t io_need = ((p.total_len + 255) & ~255LL) + k * ((aln_cap + 255) & ~255LL) + 256;
   if (c.ws_bytes < p.bytes) {
     if (c.ws) (void)hipFree(c.ws);
     c.ws = nullptr;
@@ -271,17 +290,37 @@ extern "C" int msa_dp_align_ex(const uint8_t *const *seqs, const int32_t *lens, 
     for (int i = 0; i < k; ++i) c.lens[i] = lens[i];
     c.sub.assign(submat, submat + (size_t)alpha * alpha);
   }
-  uint8_t *d_seqs = c.io;
-  uint8_t *d_aln = d_seqs + ((p.total_len + 255) & ~255LL);
-  int64_t *d_misc = (int64_t *)(d_aln + k * ((aln_cap + 255) & ~255LL));
   int64_t off = 0;
   for (int i = 0; i < k; ++i) {
     if (lens[i] > 0 &&
-        hipMemcpyAsync(d_seqs + off, seqs[i], lens[i], hipMemcpyHostToDevice, c.stream) !=
+        hipMemcpyAsync(c.io + off, seqs[i], lens[i], hipMemcpyHostToDevice, c.stream) !=
             hipSuccess)
       return MSA_EDEVICE;
     off += lens[i];
   }
+  return MSA_OK;
+}
+
+extern "C" int msa_dp_align_ex(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
+                               const int8_t *submat, int32_t alpha, int32_t gap, uint32_t flags,
+                               int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
+                               int64_t *aln_len_out) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!seqs || !score_out || !aln_len_out) return MSA_EINVAL;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  rc = check_flags(p, flags);
+  if (rc) return rc;
+  if (aln_cap < p.total_len || (p.total_len > 0 && !aln_out)) return MSA_EINVAL;
+  const int64_t io_need = ((p.total_len + 255) & ~255LL) + k * ((aln_cap + 255) & ~255LL) + 256;
+  rc = host_call_setup(seqs, lens, k, submat, alpha, gap, flags, p, io_need);
+  if (rc) return rc;
+  HostCache &c = g_cache;
+  uint8_t *d_seqs = c.io;
+  uint8_t *d_aln = d_seqs + ((p.total_len + 255) & ~255LL);
+  int64_t *d_misc = (int64_t *)(d_aln + k * ((aln_cap + 255) & ~255LL));
   rc = run_plain(p, (char *)c.ws, d_seqs, d_misc, d_aln, aln_cap, d_misc + 1,
                  (int32_t *)(d_misc + 2), c.stream);
   if (rc) return rc;
@@ -310,4 +349,55 @@ extern "C" int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int
                             int64_t *aln_len_out) {
   return msa_dp_align_ex(seqs, lens, k, submat, alpha, gap, 0u, score_out, aln_out, aln_cap,
                          aln_len_out);
+}
+
+extern "C" int msa_dp_align_coopt(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
+                                  const int8_t *submat, int32_t alpha, int32_t gap,
+                                  int32_t max_paths, int64_t *score_out, uint8_t *aln_out,
+                                  int64_t aln_cap, int64_t *aln_len_out, int32_t *npaths_out) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!seqs || !score_out || !aln_len_out || !npaths_out || !aln_out || max_paths < 1)
+    return MSA_EINVAL;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  rc = check_flags(p, MSA_COOPTIMAL);
+  if (rc) return rc;
+  if (aln_cap < p.total_len) return MSA_EINVAL;
+  // device I/O: seqs | max_paths blocks of k rows | lengths | score, npaths, status
+  const int64_t seq_b = (p.total_len + 255) & ~255LL;
+  const int64_t blk = (int64_t)k * aln_cap;
+  if (blk > 0 && max_paths > (INT64_MAX / 4) / blk) return MSA_ENOMEM;
+  const int64_t aln_b = ((int64_t)max_paths * blk + 255) & ~255LL;
+  const int64_t len_b = ((int64_t)max_paths * 8 + 255) & ~255LL;
+  const int64_t io_need = seq_b + aln_b + len_b + 256;
+  rc = host_call_setup(seqs, lens, k, submat, alpha, gap, MSA_COOPTIMAL, p, io_need);
+  if (rc) return rc;
+  HostCache &c = g_cache;
+  uint8_t *d_seqs = c.io;
+  uint8_t *d_aln = d_seqs + seq_b;
+  int64_t *d_len = (int64_t *)(d_aln + aln_b);
+  int64_t *d_misc = (int64_t *)((char *)d_len + len_b);  // score | npaths | status
+  rc = run_coopt(p, (char *)c.ws, d_seqs, max_paths, d_misc, d_aln, aln_cap, d_len,
+                 (int32_t *)(d_misc + 1), (int32_t *)(d_misc + 2), c.stream);
+  if (rc) return rc;
+  int64_t misc[3] = {0, 0, 0};
+  if (hipMemcpyAsync(misc, d_misc, sizeof(misc), hipMemcpyDeviceToHost, c.stream) !=
+      hipSuccess)
+    return MSA_EDEVICE;
+  if (hipStreamSynchronize(c.stream) != hipSuccess) return MSA_EDEVICE;
+  const int32_t st = (int32_t)(misc[2] & 0xffffffff);
+  if (st != MSA_OK) return st;
+  const int32_t np = (int32_t)(misc[1] & 0xffffffff);
+  if (np < 1 || np > max_paths) return MSA_EDEVICE;
+  if (hipMemcpyAsync(aln_len_out, d_len, (size_t)np * 8, hipMemcpyDeviceToHost, c.stream) !=
+          hipSuccess ||
+      (blk > 0 && hipMemcpyAsync(aln_out, d_aln, (size_t)(np * blk), hipMemcpyDeviceToHost,
+                                 c.stream) != hipSuccess))
+    return MSA_EDEVICE;
+  if (hipStreamSynchronize(c.stream) != hipSuccess) return MSA_EDEVICE;
+  *score_out = misc[0];
+  *npaths_out = np;
+  return MSA_OK;
 }

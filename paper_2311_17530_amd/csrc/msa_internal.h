@@ -62,15 +62,21 @@ struct Ctrl {
   int32_t status;   // MSA_OK, MSA_EINVAL (bad code), MSA_EDEVICE (watchdog)
   int32_t alpha;    // scoring fixed at set-up (plain path)
   int32_t gap;
-  int32_t flags;    // kEndGapsFree (plain path, set at set-up)
+  int32_t flags;    // kEndGapsFree / kCoOptimal (plain path, set at set-up)
   int64_t best;     // end-gap-free: max of (score << 32 | row-major cell index)
                     // over the far faces; INT64_MIN between launches
   int32_t pad[56];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte slot");
 
-// Alignment mode bit (same value as MSA_END_GAPS_FREE in the C ABI).
+// Alignment mode bits (same values as MSA_END_GAPS_FREE / MSA_COOPTIMAL in
+// the C ABI).
 constexpr int32_t kEndGapsFree = 1;
+constexpr int32_t kCoOptimal = 2;
+// Co-optimal mode: tie sets fit a byte for k <= 3, and the enumeration keeps
+// its stack of masks (one per column, at most sum n_i) in LDS.
+constexpr int kCoMaxK = 3;
+constexpr int kCoMaxTotal = 32768;
 
 // One entry of the batched tile queue: (job index, tile linear index).
 struct QItem {

@@ -164,13 +164,16 @@ __device__ inline void shift_in(uint32_t (&d)[NR], uint32_t byte) {
 // ---------------------------------------------------------------------------
 // One tile of the fill.
 // ---------------------------------------------------------------------------
+// coopt: co-optimal mode (plain path, k <= 3): the direction byte of a cell is
+// its tie set, bit b - 1 for every mask b whose candidate reaches the maximum
+// (the origin's is 0).
 // egf: end-gap-free mode (plain path): tiles with some c_i = 0 hold the cells
 // with some v_i = 0, which score 0 with no decision; tiles on a far face fold
 // their far-face cells into *best as (score << 32 | row-major cell index).
 template <int K, int NT, int SYNC>
 __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int epoch,
                              Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm, bool egf = false,
-                             int64_t *best_key = nullptr) {
+                             int64_t *best_key = nullptr, bool coopt = false) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int E = C::E;
@@ -359,9 +362,9 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     for (int i = 0; i < K; ++i) s += C::sstride(i);
     sm.S[s] = 0;
     if constexpr (C::REGDIR)
-      dr[0][0] = tid == 0 ? (uint32_t)M : 0u;  // decodes to mask 0
+      dr[0][0] = tid == 0 ? (coopt ? 0u : (uint32_t)M) : 0u;  // mask 0 / empty tie set
     else
-      sm.DIRB[0] = (uint8_t)M;
+      sm.DIRB[0] = (uint8_t)(coopt ? 0 : M);
   } else {
     constexpr int ML = C::ML;
     constexpr int NPL = KL * (KL - 1) / 2;  // pairs within the line dimensions
@@ -451,6 +454,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
           for (int bp = 1; bp <= ML; ++bp) nowv[bp] = sm.S[p - C::off(bp)];
         }
         int32_t best = INT32_MIN;
+        int32_t cand[M <= 8 ? M + 1 : 1];  // kept for tie sets (k <= 3)
 #pragma unroll
         for (int b = 1; b <= M; ++b) {
           const int bp = b & ML;
@@ -480,6 +484,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
             pred = hasL ? prv[u][bp] : nowv[bp];
           else
             pred = sm.S[p - C::off(b)];
+          if constexpr (M <= 8) cand[b] = pred + col;
           best = max(best, pred + col);
           // large k: at most 32 neighbour reads in flight (register pressure)
           if constexpr (M > 63)
@@ -487,6 +492,15 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
         }
         if (zero_tile) best = M;  // key 0; the byte decodes to mask 0
         const int32_t sv = best & ~M;
+        uint32_t byte = (uint32_t)best & 0xFFu;
+        if constexpr (M <= 8) {
+          if (coopt) {  // tie set: every candidate with the maximal score
+            byte = 0;
+#pragma unroll
+            for (int b = 1; b <= M; ++b)
+              byte |= ((cand[b] & ~M) == sv ? 1u : 0u) << (b - 1);
+          }
+        }
         sm.S[p] = sv;
         if constexpr (C::CARRY) {
           prv[u][0] = sv;
@@ -494,9 +508,9 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
           for (int bp = 1; bp <= ML; ++bp) prv[u][bp] = nowv[bp];
         }
         if constexpr (C::REGDIR)
-          shift_in<NR>(dr[u], (uint32_t)best & 0xFFu);
+          shift_in<NR>(dr[u], byte);
         else
-          sm.DIRB[(tid + u * NT) * T + t] = (uint8_t)best;
+          sm.DIRB[(tid + u * NT) * T + t] = (uint8_t)byte;
       }
       __syncthreads();
     }
@@ -672,7 +686,9 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
   __shared__ Smem<K> sm;
   const int alpha = ctrl->alpha;
   const int gap = ctrl->gap;
-  const bool egf = (__builtin_amdgcn_readfirstlane(ctrl->flags) & kEndGapsFree) != 0;
+  const int mode = __builtin_amdgcn_readfirstlane(ctrl->flags);
+  const bool egf = (mode & kEndGapsFree) != 0;
+  const bool coopt = (mode & kCoOptimal) != 0;
   load_tables<K, NT>(jd, alpha, sm);
   const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
@@ -692,7 +708,7 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
     __syncthreads();
     if (qi >= jd.ntiles) break;
     process_tile<K, NT, SYNC>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]), epoch,
-                              ctrl, &ctrl->status, sm, egf, &ctrl->best);
+                              ctrl, &ctrl->status, sm, egf, &ctrl->best, coopt);
   }
 }
 
@@ -703,9 +719,11 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
 // row-major index of the end cell).  The walk then starts at that cell, stops
 // at the first cell with some v_i = 0, and the unaligned suffixes and prefixes
 // become one-residue columns (sequence 0 first in the output).
+// coopt: the direction bytes are tie sets; the walk takes the lowest mask of
+// each, which is the decision of the plain mode.
 template <int K>
 __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb, bool egf = false,
-                              int64_t best = 0) {
+                              int64_t best = 0, bool coopt = false) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int M = C::M;
@@ -799,7 +817,7 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb, bo
     while (!done && !leave) {
       // every lane walks the same path: keep the walk state wave-uniform
       const int byte = __builtin_amdgcn_readfirstlane(dirb[d]);
-      const int b = M - (byte & M);
+      const int b = coopt ? (byte ? __builtin_ctz(byte) + 1 : 0) : M - (byte & M);
       int vor = 0, qor = 0;
       bool anyz = false;
 #pragma unroll
@@ -903,8 +921,10 @@ template <int K>
 __global__ __launch_bounds__(64) void traceback_kernel(JobDev jd, Ctrl *ctrl) {
   __shared__ alignas(16) uint8_t dirb[Cfg<K>::DBS];
   const bool egf = (ctrl->flags & kEndGapsFree) != 0;
+  const bool coopt = (ctrl->flags & kCoOptimal) != 0;
   traceback_job<K>(jd, __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                   dirb, egf, __hip_atomic_load(&ctrl->best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                   dirb, egf, __hip_atomic_load(&ctrl->best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                   coopt);
   __syncthreads();
   if (threadIdx.x == 0) {
     // ready the control block for the next launch on this workspace
@@ -915,9 +935,157 @@ __global__ __launch_bounds__(64) void traceback_kernel(JobDev jd, Ctrl *ctrl) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Co-optimal alignments (co-optimal mode, k <= 3): one wave walks depth first
+// from the far corner along tie-set masks, trying the masks of each cell in
+// ascending order.  Every such walk reaches the origin with the optimal score
+// and every optimal alignment is one, so the alignments come in lexicographic
+// order of their column masks read from the last column to the first (the
+// first is the plain traceback's).  The stack of chosen masks lives in LDS
+// (sum n_i <= kCoMaxTotal); the direction block of the current cell's tile is
+// cached in LDS.  Alignment p goes to aln_out + p * k * aln_cap.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(64) void coopt_kernel(JobDev jd, Ctrl *ctrl, int32_t max_paths,
+                                                   uint8_t *aln_out, int64_t *len_out,
+                                                   int32_t *npaths_out) {
+  using C = Cfg<K>;
+  constexpr int T = C::T;
+  constexpr int M = C::M;
+  constexpr int NQ = C::DBS / 16;
+  __shared__ alignas(16) uint8_t dirb[C::DBS];
+  __shared__ uint8_t path[kCoMaxTotal];
+  const int tid = threadIdx.x;
+  int status = __builtin_amdgcn_readfirstlane(
+      __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  // the blocks hold tie sets only when the workspace was set up for them
+  if (status == ST_OK && !(ctrl->flags & kCoOptimal)) status = ST_EINVAL;
+  int v[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = jd.n[i];
+  int64_t cur_t = -1;  // tile whose block is in dirb
+  int d = 0, np = 0;
+  int tried = 0;       // masks up to this one were tried at depth d
+  int64_t steps = 0;
+  const int64_t step_limit = (int64_t)max_paths * (2 * jd.total_len + 2) + 2;
+  while (status == ST_OK) {
+    bool origin = true;
+#pragma unroll
+    for (int i = 0; i < K; ++i) origin = origin && v[i] == 0;
+    if (origin) {
+      // emit path[0..d) (path[d-1] is the first column) as alignment np
+      uint8_t *blk = aln_out + (int64_t)np * K * jd.aln_cap;
+      int cnt[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) cnt[i] = 0;
+      for (int c0 = 0; c0 < d; c0 += 64) {
+        const int col = c0 + tid;
+        const int m = col < d ? path[d - 1 - col] : 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          const int bit = (m >> i) & 1;
+          int incl = bit;
+          for (int s = 1; s < 64; s <<= 1) {
+            const int y = __shfl_up(incl, s, 64);
+            if (tid >= s) incl += y;
+          }
+          const int pos = cnt[i] + incl - bit;
+          if (col < d)
+            blk[(int64_t)i * jd.aln_cap + col] = bit ? jd.seqs[jd.seq_off[i] + pos] : (uint8_t)0xFF;
+          cnt[i] += __shfl(incl, 63, 64);
+        }
+      }
+      if (tid == 0) len_out[np] = d;
+      ++np;
+      if (np == max_paths || d == 0) break;
+      --d;  // back up one step and try the next tied mask there
+      tried = path[d];
+#pragma unroll
+      for (int i = 0; i < K; ++i) v[i] += (tried >> i) & 1;
+      continue;
+    }
+    if (++steps > step_limit) {  // corrupt tie data: never loop for ever
+      status = ST_EDEVICE;
+      break;
+    }
+    // tie set of cell v (its tile's block cached in LDS)
+    int64_t t = 0;
+    int dl = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int ci = v[i] == 0 ? 0 : (v[i] - 1) / T + 1;
+      t += (int64_t)ci * jd.tstride[i];
+      dl += (v[i] - (ci == 0 ? 0 : (ci - 1) * T + 1)) * C::dstride(i);
+    }
+    if (t != cur_t) {
+      __syncthreads();
+      const uint4 *src = reinterpret_cast<const uint4 *>(jd.dir + t * C::DBS);
+      uint4 *dst = reinterpret_cast<uint4 *>(dirb);
+      for (int idx = tid; idx < NQ; idx += 64) dst[idx] = src[idx];
+      __syncthreads();
+      cur_t = t;
+    }
+    // tie bits 0 .. M - 1 (bit b - 1 for mask b)
+    const int ties = __builtin_amdgcn_readfirstlane(dirb[dl]) & ((1 << M) - 1);
+    const int rest = ties & ~((1 << tried) - 1);  // masks above `tried`
+    if (rest != 0) {
+      const int b = __builtin_ctz(rest) + 1;
+      bool bad = d >= jd.total_len;
+#pragma unroll
+      for (int i = 0; i < K; ++i) bad = bad || (((b >> i) & 1) && v[i] == 0);
+      if (bad) {
+        status = ST_EDEVICE;
+        break;
+      }
+      if (tid == 0) path[d] = (uint8_t)b;
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < K; ++i) v[i] -= (b >> i) & 1;
+      ++d;
+      tried = 0;
+      continue;
+    }
+    if (ties == 0 && tried == 0) {  // a cell other than the origin with no tie
+      status = ST_EDEVICE;
+      break;
+    }
+    if (d == 0) break;  // every alignment has been produced
+    --d;
+    tried = path[d];
+#pragma unroll
+    for (int i = 0; i < K; ++i) v[i] += (tried >> i) & 1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    *npaths_out = status == ST_OK ? np : 0;
+    *jd.status_out = status;
+    if (status != ST_OK) *jd.score_out = 0;
+    // ready the control block for the next launch on this workspace
+    ctrl->head = 0;
+    ctrl->status = ST_OK;
+    ctrl->best = INT64_MIN;
+    ctrl->epoch = ctrl->epoch + 1;
+  }
+}
+
+template <int K>
+static int launch_coopt_k(const JobDev &jd, Ctrl *ctrl, int32_t max_paths, uint8_t *aln_out,
+                          int64_t *len_out, int32_t *npaths_out, hipStream_t s) {
+  if constexpr (K <= 3) {
+    hipLaunchKernelGGL((coopt_kernel<K>), dim3(1), dim3(64), 0, s, jd, ctrl, max_paths, aln_out,
+                       len_out, npaths_out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  } else {
+    return -1;
+  }
+}
+
 // Row-major decision tensor (mask b per cell) from the tile-major blocks.
 template <int K>
-__global__ void export_dirs_kernel(JobDev jd, uint8_t *out, int64_t ncell) {
+// A co-optimal workspace exports the bytes as stored (the tie sets) instead
+// of decoding them to the chosen mask.
+__global__ void export_dirs_kernel(JobDev jd, const Ctrl *ctrl, uint8_t *out, int64_t ncell) {
+  const bool raw = (ctrl->flags & kCoOptimal) != 0;
   using C = Cfg<K>;
   constexpr int T = C::T;
   for (int64_t lin = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; lin < ncell;
@@ -938,7 +1106,7 @@ __global__ void export_dirs_kernel(JobDev jd, uint8_t *out, int64_t ncell) {
       d += (v[i] - loi) * C::dstride(i);
     }
     const int byte = jd.dir[(int64_t)t * C::DBS + d];
-    out[lin] = (uint8_t)(C::M - (byte & C::M));
+    out[lin] = raw ? (uint8_t)byte : (uint8_t)(C::M - (byte & C::M));
   }
 }
 
@@ -1131,12 +1299,13 @@ static int occupancy_k() {
 }
 
 template <int K>
-static int launch_export_k(const JobDev &jd, uint8_t *out, int64_t ncell, hipStream_t s) {
+static int launch_export_k(const JobDev &jd, const Ctrl *ctrl, uint8_t *out, int64_t ncell,
+                           hipStream_t s) {
   int64_t blocks = (ncell + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((export_dirs_kernel<K>), dim3((unsigned)blocks), dim3(256), 0, s, jd, out,
-                     ncell);
+  hipLaunchKernelGGL((export_dirs_kernel<K>), dim3((unsigned)blocks), dim3(256), 0, s, jd, ctrl,
+                     out, ncell);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1162,8 +1331,14 @@ int launch_traceback(const JobDev &jd, Ctrl *ctrl, hipStream_t s) {
 
 int fill_occupancy(int k) { MSA_DISPATCH_K(k, occupancy_k); }
 
-int launch_export(const JobDev &jd, uint8_t *out, int64_t ncell, hipStream_t s) {
-  MSA_DISPATCH_K(jd.k, launch_export_k, jd, out, ncell, s);
+int launch_coopt(const JobDev &jd, Ctrl *ctrl, int32_t max_paths, uint8_t *aln_out,
+                 int64_t *len_out, int32_t *npaths_out, hipStream_t s) {
+  MSA_DISPATCH_K(jd.k, launch_coopt_k, jd, ctrl, max_paths, aln_out, len_out, npaths_out, s);
+}
+
+int launch_export(const JobDev &jd, const Ctrl *ctrl, uint8_t *out, int64_t ncell,
+                  hipStream_t s) {
+  MSA_DISPATCH_K(jd.k, launch_export_k, jd, ctrl, out, ncell, s);
 }
 
 }  // namespace msa

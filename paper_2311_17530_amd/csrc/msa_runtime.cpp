@@ -68,20 +68,7 @@ static int64_t *g_trace_buf = nullptr;
 extern "C" void msa_dp_debug_set_trace(int64_t *d_buf) { g_trace_buf = d_buf; }
 #endif
 
-int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, uint8_t *d_aln,
-              int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,
-              int which) {
-  JobDev jd;
-  fill_jobdev(p, ws, 0, 0, &jd);  // alpha and gap are read from the control block
-  jd.seqs = d_seqs;
-  jd.score_out = d_score;
-  jd.aln_out = d_aln;
-  jd.aln_cap = aln_cap;
-  jd.aln_len_out = d_aln_len;
-  jd.status_out = d_status;
-#ifdef MSA_TRACE
-  jd.trace = g_trace_buf;
-#endif
+static int fill_grid(const Plan &p) {
   // Persistent workgroups: as many tiles as the widest wave holds, rounded
   // down to whole compute units, at least one per unit and at most what
   // fits.  Beyond the widest wave extra workgroups only wait, and tiles that
@@ -98,17 +85,51 @@ int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, 
   if (grid > cu * occupancy(p.k)) grid = cu * occupancy(p.k);
   if (grid > p.ntiles) grid = p.ntiles;
   if (grid < 1) grid = 1;
+  return (int)grid;
+}
+
+int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, uint8_t *d_aln,
+              int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,
+              int which) {
+  JobDev jd;
+  fill_jobdev(p, ws, 0, 0, &jd);  // alpha and gap are read from the control block
+  jd.seqs = d_seqs;
+  jd.score_out = d_score;
+  jd.aln_out = d_aln;
+  jd.aln_cap = aln_cap;
+  jd.aln_len_out = d_aln_len;
+  jd.status_out = d_status;
+#ifdef MSA_TRACE
+  jd.trace = g_trace_buf;
+#endif
   Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
   const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
-  if ((which & 1) && launch_fill(jd, ctrl, order, (int)grid, s) != 0) return MSA_EDEVICE;
+  if ((which & 1) && launch_fill(jd, ctrl, order, fill_grid(p), s) != 0) return MSA_EDEVICE;
   if ((which & 2) && launch_traceback(jd, ctrl, s) != 0) return MSA_EDEVICE;
+  return MSA_OK;
+}
+
+int run_coopt(const Plan &p, char *ws, const uint8_t *d_seqs, int32_t max_paths, int64_t *d_score,
+              uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len, int32_t *d_npaths,
+              int32_t *d_status, hipStream_t s) {
+  JobDev jd;
+  fill_jobdev(p, ws, 0, 0, &jd);
+  jd.seqs = d_seqs;
+  jd.score_out = d_score;
+  jd.aln_cap = aln_cap;
+  jd.status_out = d_status;
+  Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
+  const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
+  if (launch_fill(jd, ctrl, order, fill_grid(p), s) != 0) return MSA_EDEVICE;
+  if (launch_coopt(jd, ctrl, max_paths, d_aln, d_aln_len, d_npaths, s) != 0) return MSA_EDEVICE;
   return MSA_OK;
 }
 
 int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s) {
   JobDev jd;
   fill_jobdev(p, ws, 0, 0, &jd);
-  return launch_export(jd, out, p.ncell, s) == 0 ? MSA_OK : MSA_EDEVICE;
+  const Ctrl *ctrl = reinterpret_cast<const Ctrl *>(ws + p.off_ctrl);
+  return launch_export(jd, ctrl, out, p.ncell, s) == 0 ? MSA_OK : MSA_EDEVICE;
 }
 
 }  // namespace msa

@@ -10,7 +10,10 @@ namespace msa {
 // kernels (msa_kernels.hip)
 int launch_fill(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, hipStream_t s);
 int launch_traceback(const JobDev &jd, Ctrl *ctrl, hipStream_t s);
-int launch_export(const JobDev &jd, uint8_t *out, int64_t ncell, hipStream_t s);
+int launch_export(const JobDev &jd, const Ctrl *ctrl, uint8_t *out, int64_t ncell,
+                  hipStream_t s);
+int launch_coopt(const JobDev &jd, Ctrl *ctrl, int32_t max_paths, uint8_t *aln_out,
+                 int64_t *len_out, int32_t *npaths_out, hipStream_t s);
 int fill_occupancy(int k);
 int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_jtiles,
                  int32_t *qjob, int32_t *qtile, int64_t total, int32_t *flags, Ctrl *ctrl,
@@ -26,5 +29,10 @@ int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, 
               int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,
               int which = 3);
 int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s);
+// fill, then up to max_paths co-optimal alignments (workspace prepared with
+// the co-optimal flag)
+int run_coopt(const Plan &p, char *ws, const uint8_t *d_seqs, int32_t max_paths, int64_t *d_score,
+              uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len, int32_t *d_npaths,
+              int32_t *d_status, hipStream_t s);
 
 }  // namespace msa

@@ -134,9 +134,11 @@ def test_mode_flags_rejected_before_device():
     lens = (ctypes.c_int32 * 2)(3, 3)
     out = np.zeros((2, 6), np.uint8)
     score, alen = ctypes.c_int64(), ctypes.c_int64()
-    rc = msa.lib().msa_dp_align_ex(ptrs, lens, 2, sub8.ctypes.data, 4, gap, 2,
-                                   ctypes.byref(score), out.ctypes.data, 6, ctypes.byref(alen))
-    assert rc == msa.MSA_EINVAL  # undefined flag bit
+    for flags in (4, 1 | 2):  # an undefined bit; end-gap-free with co-optimal
+        rc = msa.lib().msa_dp_align_ex(ptrs, lens, 2, sub8.ctypes.data, 4, gap, flags,
+                                       ctypes.byref(score), out.ctypes.data, 6,
+                                       ctypes.byref(alen))
+        assert rc == msa.MSA_EINVAL
     # end-gap-free keys hold the cell index in 32 bits
     big = [np.zeros(70000, np.uint8)] * 2
     with pytest.raises(msa.MsaError) as e:
@@ -145,3 +147,37 @@ def test_mode_flags_rejected_before_device():
     ws = 256  # any aligned address: rejected before it is touched
     rc = msa.lib().msa_dp_prepare_ex(ws, 1 << 40, lens, 2, sub8.ctypes.data, 4, gap, 4, None)
     assert rc == msa.MSA_EINVAL
+
+
+def test_coopt_limits_rejected_before_device():
+    # tie sets fit a byte for k <= 3; the walk's mask stack holds 32768 columns
+    sub, gap = dna_scoring()
+    a = np.array([0, 1, 2], np.uint8)
+    with pytest.raises(msa.MsaError) as e:
+        msa.align_coopt([a] * 4, sub, gap, 4)
+    assert e.value.status == msa.MSA_EINVAL
+    with pytest.raises(msa.MsaError) as e:
+        msa.align_coopt([a, a], sub, gap, 0)
+    assert e.value.status == msa.MSA_EINVAL
+    with pytest.raises(msa.MsaError) as e:
+        msa.align_coopt([np.zeros(16385, np.uint8)] * 2, sub, gap, 1)
+    assert e.value.status == msa.MSA_ERANGE
+    with pytest.raises(msa.MsaError) as e:
+        _align_ex([a] * 4, sub, gap, msa.MSA_COOPTIMAL)
+    assert e.value.status == msa.MSA_EINVAL
+
+
+def _align_ex(seqs, sub, gap, flags):
+    import ctypes
+    sub8 = np.ascontiguousarray(np.asarray(sub, np.int8))
+    k = len(seqs)
+    ptrs = (ctypes.c_void_p * k)(*[s.ctypes.data for s in seqs])
+    lens = (ctypes.c_int32 * k)(*[len(s) for s in seqs])
+    cap = sum(len(s) for s in seqs)
+    out = np.zeros((k, cap), np.uint8)
+    score, alen = ctypes.c_int64(), ctypes.c_int64()
+    rc = msa.lib().msa_dp_align_ex(ptrs, lens, k, sub8.ctypes.data, sub8.shape[0], gap, flags,
+                                   ctypes.byref(score), out.ctypes.data, cap,
+                                   ctypes.byref(alen))
+    if rc != msa.MSA_OK:
+        raise msa.MsaError(rc, "msa_dp_align_ex")

@@ -1,5 +1,5 @@
-"""Pins for the oracle's co-optimal enumeration (Section 6: further optimal
-solutions by forking at equally ranked paths).
+"""Pins for the oracle's co-optimal enumeration (Section 6 proposes a
+traceback that branches wherever several choices tie).
 
 - exhaustive enumeration of every alignment of tiny k = 2, 3 inputs: the list
   of optimal alignments, in the same order (column masks read from the last

@@ -1,5 +1,5 @@
-"""Pins for the oracle's end-gap-free variant (the reading of the traceback
-start "from the highest score on the bottom edges", Section 2).
+"""Pins for the oracle's end-gap-free variant (the reading of Section 2's
+traceback start at the best-scoring cell of the far boundary).
 
 - hand-worked cases (tests/golden/egf_cases.json);
 - k = 2 equals textbook overlap (semi-global) alignment, written
