@@ -109,8 +109,8 @@ def brute_force_align(seqs, sub, gap):
 def brute_force_egf_score(seqs, sub, gap):
     """Best end-gap-free score by enumeration, independent of any recurrence.
 
-    End-gap-free reading of the traceback start ("highest score on the bottom
-    edges", Section 2): an alignment may leave a prefix and a suffix of the
+    End-gap-free reading of Section 2's traceback start (the best-scoring cell
+    of the far boundary): an alignment may leave a prefix and a suffix of the
     sequences unaligned for free.  The aligned part (the core) aligns the
     substrings s_i[a_i:e_i] where the start a has some a_i = 0 (a prefix of
     every sequence but at least one is skipped) and the end e >= a has some

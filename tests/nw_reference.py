@@ -60,3 +60,18 @@ def semiglobal_nw_score(a, b, sub, g):
             F[i, j] = max(F[i - 1, j] + g, F[i, j - 1] + g,
                           F[i - 1, j - 1] + int(sub[a[i - 1]][b[j - 1]]))
     return int(max(F[n, :].max(), F[:, m].max()))
+
+
+def nw_score_table(a, b, sub, g):
+    """F[i, j] = best score of aligning a[:i] with b[:j] (the table above)."""
+    n, m = len(a), len(b)
+    F = np.zeros((n + 1, m + 1), dtype=np.int64)
+    for i in range(1, n + 1):
+        F[i, 0] = i * g
+    for j in range(1, m + 1):
+        F[0, j] = j * g
+    for i in range(1, n + 1):
+        for j in range(1, m + 1):
+            F[i, j] = max(F[i - 1, j] + g, F[i, j - 1] + g,
+                          F[i - 1, j - 1] + int(sub[a[i - 1]][b[j - 1]]))
+    return F
