@@ -16,7 +16,8 @@ already resident in HBM.  Prints one JSON line:
                full k=3 / 512 alignment
 
 The same numbers for the k=4 / 128 workload (129^4 cells) and for the k=3
-workload in end-gap-free mode are reported under "extra"; "batched" gives jobs/s of the 4096-job workload through the batched
+workload in end-gap-free mode, and the k=3 workload's co-optimal mode (tie-set
+fill plus the first 16 co-optimal alignments), are reported under "extra"; "batched" gives jobs/s of the 4096-job workload through the batched
 persistent launches (beside sequential plain calls), "served" the saturated
 throughput and p50/p99 latency of a 20000-job Poisson stream through the
 server at 0.7 times that rate.  Only one GPU is used: --gpus above 1 is
@@ -84,6 +85,38 @@ def time_workload(name, steps, warmup, end_gaps_free=False):
         fill_tops=2 * nu / (fill_avg / 1e3) / 1e12,
         score=score, aln_len=int(rows.shape[1]),
         tile_edge=msa.tile_edge(job.k))
+
+
+def time_coopt(name, steps, warmup, max_paths=16):
+    """Whole step of the co-optimal mode: the fill keeping tie sets, then the
+    enumeration of the first ``max_paths`` co-optimal alignments."""
+    import torch
+    import paper_2311_17530_amd as msa
+    from msa_inputs import workload
+
+    job = workload(name)
+    dev = msa.DeviceAligner(job.lens, job.sub, job.gap, cooptimal=True)
+    dev.set_sequences(job.seqs)
+    for _ in range(warmup):
+        dev.run_coopt(max_paths)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(stream)
+        dev.run_coopt(max_paths)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    score, alns = dev.result_coopt()
+    ms_per_step = wall * 1e3 / steps
+    return dict(workload=name + " co-optimal", k=job.k, lens=job.lens, cells=job.cells,
+                max_paths=max_paths, alignments=len(alns), ms_per_step=ms_per_step,
+                step_ms_avg=float(np.mean(step_ms)),
+                gcups=job.cells / (ms_per_step / 1e3) / 1e9, score=score)
 
 
 def bench_batched(n_jobs=4096, n_plain=256):
@@ -248,6 +281,8 @@ def main():
         # the end-gap-free mode on the same workload (same fill, zero faces,
         # far-face maximum, traceback to the first face)
         extra[MAIN + "_end_gaps_free"] = time_workload(MAIN, a.steps, a.warmup, True)
+        # co-optimal mode: tie-set fill and the first 16 co-optimal alignments
+        extra[MAIN + "_cooptimal"] = time_coopt(MAIN, a.steps, a.warmup)
     achieved = main_r["fill_tops"]
     line = {
         "metric": "GCUPS",

@@ -60,6 +60,7 @@ enum {
 /* Alignment mode flags (the _ex entry points). */
 #define MSA_END_GAPS_FREE 1u /* end-gap-free alignment, see msa_dp_align_ex */
 #define MSA_COOPTIMAL 2u     /* tie sets kept for msa_dp_align_coopt */
+#define MSA_PRUNE 4u         /* exact tile pruning, see msa_dp_align_ex */
 
 /* Human-readable text for a status code (static storage). */
 const char *msa_strerror(int status);
@@ -96,6 +97,21 @@ int msa_dp_align(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
  *   set, bit b - 1 for mask b); the alignment returned is the same as with
  *   flags = 0.  Requires k <= 3 and sum(lens) <= 32768 (MSA_EINVAL /
  *   MSA_ERANGE otherwise); not combinable with MSA_END_GAPS_FREE (MSA_EINVAL).
+ * MSA_PRUNE: exact search-space reduction, Section 6's computation of only
+ *   the partitions (tiles) where an optimal alignment can lie, made exact
+ *   with the pairwise bound of Carrillo and Lipman: every cell v of an
+ *   alignment with score S has S <= sum_{i<j} F_ij(v_i, v_j) + G_ij(v_i, v_j)
+ *   (optimal pairwise scores of the prefixes and of the suffixes), so a tile
+ *   whose bound, the sum over pairs of the maximum of F_ij + G_ij over the
+ *   tile, is below a lower bound L of the optimum is not computed.  Pass 1
+ *   uses L1 = U - ceil(|U|/16) - C(k,2) * max(|gap|, max|sub|), U the sum of
+ *   the pairwise optima; its result is exact when its score reaches L1,
+ *   otherwise pass 2 runs with L2 = that score (a real path's score, else no
+ *   pruning).  Score and alignment equal those of flags = 0 (the decisions
+ *   along optimal alignments are unchanged); the decision bytes of other
+ *   cells may differ or be unwritten.  Requires 3 <= k <= 6 (else
+ *   MSA_EINVAL) and every length < 16384 (else MSA_ERANGE); combinable with
+ *   MSA_COOPTIMAL, not with MSA_END_GAPS_FREE (MSA_EINVAL).
  * Other flag bits: MSA_EINVAL.  Errors otherwise as msa_dp_align.
  * ---------------------------------------------------------------------- */
 int msa_dp_align_ex(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
@@ -208,6 +224,18 @@ int msa_dp_traceback_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_s
 int msa_dp_export_dirs(void *d_workspace, int64_t ws_bytes,
                        const int32_t *lens, int32_t k, uint8_t *d_dir_out,
                        void *hip_stream);
+
+/* For a workspace prepared with MSA_PRUNE, after a fill: d_keep_out (may be
+ * NULL) receives one byte per tile, 1 if the last pass computed it, in
+ * row-major order of the tile coordinates (tiles along dimension i: one for
+ * v_i = 0, then ceil(n_i / msa_dp_tile_edge(k)) of that edge); d_info_out
+ * (may be NULL) receives 4 int64: U, the last pass's threshold L (INT64_MIN
+ * for no pruning), the tiles it computed, and the passes run (1 or 2).
+ * Device buffers; asynchronous on hip_stream.  MSA_EINVAL if the workspace
+ * was not prepared with MSA_PRUNE. */
+int msa_dp_export_prune(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
+                        int32_t k, uint8_t *d_keep_out, int64_t *d_info_out,
+                        void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Batched path: many independent alignments (uneven k and lengths) through

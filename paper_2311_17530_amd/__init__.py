@@ -16,6 +16,7 @@ from ._lib import (  # noqa: F401
     MSA_ERANGE,
     MSA_ESHUTDOWN,
     MSA_OK,
+    MSA_PRUNE,
     DeviceAligner,
     MsaError,
     Server,

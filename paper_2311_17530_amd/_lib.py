@@ -58,6 +58,7 @@ class MsaResult(ctypes.Structure):
 # alignment mode flags (msa_dp_align_ex / msa_dp_prepare_ex)
 MSA_END_GAPS_FREE = 1
 MSA_COOPTIMAL = 2
+MSA_PRUNE = 4
 
 _SIGS = {
     "msa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -84,6 +85,8 @@ _SIGS = {
                                             c_vp, c_vp]),
     "msa_dp_export_dirs": (ctypes.c_int, [c_vp, ctypes.c_int64, c_i32p, ctypes.c_int32,
                                           c_vp, c_vp]),
+    "msa_dp_export_prune": (ctypes.c_int, [c_vp, ctypes.c_int64, c_i32p, ctypes.c_int32,
+                                           c_vp, c_vp, c_vp]),
     "msa_dp_coopt_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p, ctypes.c_int32,
                                         ctypes.c_int32, c_vp, c_vp, ctypes.c_int64, c_vp,
                                         c_vp, c_vp, c_vp]),
@@ -180,9 +183,9 @@ def workspace_bytes(lens) -> int:
 # ---------------------------------------------------------------------------
 # plain path, host buffers
 # ---------------------------------------------------------------------------
-def align(seqs, sub, gap, end_gaps_free: bool = False):
+def align(seqs, sub, gap, end_gaps_free: bool = False, prune: bool = False):
     """Optimal alignment through ``msa_dp_align_ex`` (host buffers);
-    ``end_gaps_free`` selects MSA_END_GAPS_FREE.
+    ``end_gaps_free`` selects MSA_END_GAPS_FREE, ``prune`` MSA_PRUNE.
 
     Returns ``(score, rows)`` with rows a (k, L) uint8 array (GAP for gaps)."""
     seqs = [np.ascontiguousarray(np.asarray(s, dtype=np.uint8)) for s in seqs]
@@ -194,7 +197,8 @@ def align(seqs, sub, gap, end_gaps_free: bool = False):
     score, alen = ctypes.c_int64(), ctypes.c_int64()
     rc = lib().msa_dp_align_ex(ptrs, _i32arr([len(s) for s in seqs]), k, sub.ctypes.data,
                                sub.shape[0], int(gap),
-                               MSA_END_GAPS_FREE if end_gaps_free else 0,
+                               (MSA_END_GAPS_FREE if end_gaps_free else 0)
+                               | (MSA_PRUNE if prune else 0),
                                ctypes.byref(score), out.ctypes.data, cap, ctypes.byref(alen))
     _check(rc, "msa_dp_align_ex")
     return int(score.value), out[:, : alen.value].copy()
@@ -231,7 +235,7 @@ class DeviceAligner:
     enqueues one alignment on the current torch stream (asynchronous)."""
 
     def __init__(self, lens, sub, gap, device="cuda", end_gaps_free: bool = False,
-                 cooptimal: bool = False):
+                 cooptimal: bool = False, prune: bool = False):
         import torch
         self.torch = torch
         self.lens = [int(x) for x in lens]
@@ -249,8 +253,8 @@ class DeviceAligner:
         self.d_score = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.d_len = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.d_status = torch.zeros(1, dtype=torch.int32, device=self.device)
-        flags = (MSA_END_GAPS_FREE if end_gaps_free else 0) | (
-            MSA_COOPTIMAL if cooptimal else 0)
+        flags = ((MSA_END_GAPS_FREE if end_gaps_free else 0)
+                 | (MSA_COOPTIMAL if cooptimal else 0) | (MSA_PRUNE if prune else 0))
         rc = lib().msa_dp_prepare_ex(self.ws_ptr, self.ws_bytes, _i32arr(self.lens), self.k,
                                      self.sub.ctypes.data, self.sub.shape[0], self.gap,
                                      flags, self._stream())
@@ -324,6 +328,22 @@ class DeviceAligner:
         L = int(self.d_len.item())
         rows = self.d_aln[:, :L].cpu().numpy()
         return int(self.d_score.item()), rows
+
+    def export_prune(self):
+        """Pruned mode: ``(keep, info)`` of the last fill -- keep flags over
+        the tile grid (array of the tile-grid shape) and
+        ``{"U", "L", "kept", "passes"}``."""
+        t = self.torch
+        P, _ = tile_grid(self.lens, tile_edge(self.k))
+        keep = t.zeros(int(np.prod(P)), dtype=t.uint8, device=self.device)
+        info = t.zeros(4, dtype=t.int64, device=self.device)
+        rc = lib().msa_dp_export_prune(self.ws_ptr, self.ws_bytes, _i32arr(self.lens), self.k,
+                                       keep.data_ptr(), info.data_ptr(), self._stream())
+        _check(rc, "msa_dp_export_prune")
+        self.torch.cuda.current_stream(self.device).synchronize()
+        v = [int(x) for x in info.cpu().tolist()]
+        return (keep.cpu().numpy().reshape(P).astype(bool),
+                {"U": v[0], "L": v[1], "kept": v[2], "passes": v[3]})
 
     def export_dirs(self):
         """Row-major decision tensor of the last run: the neighbour mask per

@@ -89,9 +89,15 @@ extern "C" int64_t msa_dp_workspace_bytes(const int32_t *lens, int32_t k) {
 // Mode flags.  The end-gap-free end-cell key holds the row-major cell index
 // in 32 bits; a co-optimal tie set fits a byte for k <= 3 and its walk keeps
 // one mask per column on chip.
+// The pruned mode needs 3 <= k <= 6 and lengths below kPruneMaxLen (its
+// pairwise bounds assume the global alignment's start and end).
 static int check_flags(const Plan &p, uint32_t flags) {
-  if (flags & ~(uint32_t)(MSA_END_GAPS_FREE | MSA_COOPTIMAL)) return MSA_EINVAL;
-  if ((flags & MSA_END_GAPS_FREE) && (flags & MSA_COOPTIMAL)) return MSA_EINVAL;
+  if (flags & ~(uint32_t)(MSA_END_GAPS_FREE | MSA_COOPTIMAL | MSA_PRUNE)) return MSA_EINVAL;
+  if ((flags & MSA_END_GAPS_FREE) && (flags & (MSA_COOPTIMAL | MSA_PRUNE))) return MSA_EINVAL;
+  if (flags & MSA_PRUNE) {
+    if (p.k < kPruneMinK || p.k > kPruneMaxK) return MSA_EINVAL;
+    if (!p.prunable) return MSA_ERANGE;
+  }
   if ((flags & MSA_END_GAPS_FREE) && p.ncell > ((int64_t)1 << 32)) return MSA_ERANGE;
   if (flags & MSA_COOPTIMAL) {
     if (p.k > kCoMaxK) return MSA_EINVAL;
@@ -184,6 +190,19 @@ extern "C" int msa_dp_export_dirs(void *d_workspace, int64_t ws_bytes, const int
   if (rc) return rc;
   if (ws_bytes < p.bytes) return MSA_EINVAL;
   return export_dirs(p, (char *)d_workspace, d_dir_out, (hipStream_t)hip_stream);
+}
+
+extern "C" int msa_dp_export_prune(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
+                                   int32_t k, uint8_t *d_keep_out, int64_t *d_info_out,
+                                   void *hip_stream) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!d_workspace || (!d_keep_out && !d_info_out)) return MSA_EINVAL;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  if (ws_bytes < p.bytes) return MSA_EINVAL;
+  return export_prune(p, (char *)d_workspace, d_keep_out, d_info_out, (hipStream_t)hip_stream);
 }
 
 extern "C" int msa_dp_coopt_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,

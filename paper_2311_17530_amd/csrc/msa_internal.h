@@ -47,6 +47,7 @@ struct JobDev {
   int64_t aln_cap;
   int64_t *aln_len_out;
   int32_t *status_out;
+  const uint8_t *keep;        // pruned mode: per-tile keep flags (else null)
   int64_t *trace;             // optional per-tile phase timestamps (debug builds)
   // batched path only
   int32_t *jstatus;           // per-job status (bad residue code)
@@ -65,7 +66,14 @@ struct Ctrl {
   int32_t flags;    // kEndGapsFree / kCoOptimal (plain path, set at set-up)
   int64_t best;     // end-gap-free: max of (score << 32 | row-major cell index)
                     // over the far faces; INT64_MIN between launches
-  int32_t pad[56];
+  // pruned mode (tile bounds): U = sum of pairwise optima, the threshold of
+  // the last pass, tiles kept by it and the number of passes run
+  int64_t prune_U, prune_L, prune_kept, prune_passes;
+  int64_t lo;       // closed-form lower bound of every score (set-up)
+  int64_t prune_c;  // C(k,2) * max(|gap|, max |sub|) (set-up)
+  int32_t nqueue;   // tiles in the pruned queue
+  int32_t redo;     // 1 when the first pruned pass missed its threshold
+  int32_t pad[42];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte slot");
 
@@ -73,6 +81,38 @@ static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte slot");
 // the C ABI).
 constexpr int32_t kEndGapsFree = 1;
 constexpr int32_t kCoOptimal = 2;
+constexpr int32_t kPrune = 4;
+// Pruned mode: the dependency wait covers all 2^k - 1 lower neighbour tiles
+// with one lane each (k <= 6), and the pairwise tables keep one row of
+// boundary values per band of rows in a wave's registers (n_i < kPruneMaxLen).
+constexpr int kPruneMinK = 3;
+constexpr int kPruneMaxK = 6;
+constexpr int kPruneMaxLen = 16384;
+constexpr int kMaxPairs = kPruneMaxK * (kPruneMaxK - 1) / 2;
+
+// Device descriptor of the pruning kernels (pairwise tables, tile bounds,
+// tile selection and compaction).
+struct PruneDev {
+  int32_t k, npairs, T;
+  int32_t ntiles;
+  int32_t n[kMaxK], P[kMaxK], tstride[kMaxK], seq_off[kMaxK];
+  int32_t pi[kMaxPairs], pj[kMaxPairs];  // pair p = (pi[p], pj[p]), pi < pj
+  int64_t tab_off[kMaxPairs];  // int32 offset of pair p's prefix table (suffix follows)
+  int64_t bm_off[kMaxPairs];   // int32 offset of pair p's block-maximum table
+  int32_t nblocks;             // selection blocks of kSelBlock tiles
+  const uint8_t *seqs;
+  const int8_t *sub;
+  int32_t alpha, gap;
+  int32_t *tabs;               // pairwise tables (column-major, see the kernels)
+  int32_t *bm;                 // block maxima of prefix + suffix per tile pair
+  uint8_t *keep;               // per tile (row-major tile index): kept in the last pass
+  const int32_t *order;        // tiles in computation-wave order
+  int32_t *korder;             // kept tiles in the same order
+  int32_t *bcnt;               // kept tiles per selection block, then their offsets
+  const int64_t *score;        // the fill's end score
+};
+constexpr int kSelBlock = 1024;
+
 // Co-optimal mode: tie sets fit a byte for k <= 3, and the enumeration keeps
 // its stack of masks (one per column, at most sum n_i) in LDS.
 constexpr int kCoMaxK = 3;

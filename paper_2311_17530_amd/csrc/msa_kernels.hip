@@ -170,10 +170,14 @@ __device__ inline void shift_in(uint32_t (&d)[NR], uint32_t byte) {
 // egf: end-gap-free mode (plain path): tiles with some c_i = 0 hold the cells
 // with some v_i = 0, which score 0 with no decision; tiles on a far face fold
 // their far-face cells into *best as (score << 32 | row-major cell index).
+// prune: pruned mode (plain path, k <= 6): only kept tiles (jd.keep) run; a
+// tile waits for every kept lower-neighbour tile and takes the halo cells of
+// the others as -infinity.
 template <int K, int NT, int SYNC>
 __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int epoch,
                              Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm, bool egf = false,
-                             int64_t *best_key = nullptr, bool coopt = false) {
+                             int64_t *best_key = nullptr, bool coopt = false,
+                             bool prune = false) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int E = C::E;
@@ -244,7 +248,26 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     }
   }
 
+  // ---- kept lower-neighbour tiles (pruned mode): bit S for tile c - e_S ----
+  uint64_t kbits = ~0ull;
+  if constexpr (K <= kPruneMaxK) {
+    if (prune) {
+      const int S = tid & 63;
+      bool ok = S >= 1 && S <= C::M;
+      int tn = tile;
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+        if ((S >> i) & 1) {
+          ok = ok && c[i] > 0;
+          tn -= jd.tstride[i];
+        }
+      const int kv = jd.keep[ok ? tn : tile];
+      kbits = __ballot(ok && kv != 0);
+    }
+  }
+
   // ---- wait for the k face predecessors (diagonal ones are implied) ----
+  // (pruned mode: for every kept lower neighbour, lane S polling tile c - e_S)
   // Wave 0 polls: lane i reads the flag of tile c - e_i until it has seen it
   // (a flag never goes back within a launch), so satisfied lanes stop loading.
   // The loop condition is a wave vote and every exit test is wave-uniform, so
@@ -255,11 +278,20 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
   if (wave == 0) {
     const int32_t *f = jd.flags;
     bool need = false;
+    if (K <= kPruneMaxK && prune) {
+      need = ((kbits >> (tid & 63)) & 1) != 0;
+      int tn = tile;
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      if (tid == i && c[i] > 0) {
-        need = true;
-        f = jd.flags + (tile - jd.tstride[i]);
+      for (int i = 0; i < K; ++i)
+        if ((tid >> i) & 1) tn -= jd.tstride[i];
+      f = jd.flags + (need ? tn : tile);
+    } else {
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        if (tid == i && c[i] > 0) {
+          need = true;
+          f = jd.flags + (tile - jd.tstride[i]);
+        }
       }
     }
     const int64_t t0 = wall_now();
@@ -313,6 +345,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
             int s = 0;
             bool valid = idx < cnt, neg = (c[i] == 0);
             int64_t foff = 0;
+            int src = 1 << i;  // the cell lies in tile c - e_src
 #pragma unroll
             for (int j = K - 1; j >= 0; --j) {
               if (j == i) continue;
@@ -322,12 +355,15 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
               s += l * C::sstride(j);
               const int v = lo[j] - 1 + l;
               neg = neg || v < 0;
+              src |= (l == 0 ? 1 : 0) << j;
               foff += (int64_t)v * jd.fstride[i][j];
             }
             sidx[di][it] = valid ? s : -1;
+            // a cell of a pruned tile was never computed: -infinity
+            const bool take = valid && !neg && ((kbits >> (src & 63)) & 1) != 0;
             // unconditional load from a clamped in-range offset, then select
-            const int32_t got = face_load<SYNC>(plane + ((valid && !neg) ? foff : 0));
-            val[di][it] = (valid && !neg) ? got : kNegKey;
+            const int32_t got = face_load<SYNC>(plane + (take ? foff : 0));
+            val[di][it] = take ? got : kNegKey;
           }
         }
 #pragma unroll
@@ -680,15 +716,20 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
 }
 
 // Plain path: one job, descriptor passed by value.
+// pass (pruned mode): 1 = first pass, 2 = second pass, which runs only when
+// the first missed its threshold; 0 otherwise.
 template <int K, int NT, int SYNC>
 __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
-                                                  const int32_t *__restrict__ order) {
+                                                  const int32_t *__restrict__ order, int pass) {
   __shared__ Smem<K> sm;
+  if (pass == 2 && __builtin_amdgcn_readfirstlane(ctrl->redo) == 0) return;
   const int alpha = ctrl->alpha;
   const int gap = ctrl->gap;
   const int mode = __builtin_amdgcn_readfirstlane(ctrl->flags);
   const bool egf = (mode & kEndGapsFree) != 0;
   const bool coopt = (mode & kCoOptimal) != 0;
+  const bool prune = (mode & kPrune) != 0;
+  const int nq = prune ? __builtin_amdgcn_readfirstlane(ctrl->nqueue) : jd.ntiles;
   load_tables<K, NT>(jd, alpha, sm);
   const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
@@ -706,9 +747,9 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
     __syncthreads();
     const int qi = __builtin_amdgcn_readfirstlane(bcast);
     __syncthreads();
-    if (qi >= jd.ntiles) break;
+    if (qi >= nq) break;
     process_tile<K, NT, SYNC>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]), epoch,
-                              ctrl, &ctrl->status, sm, egf, &ctrl->best, coopt);
+                              ctrl, &ctrl->status, sm, egf, &ctrl->best, coopt, prune);
   }
 }
 
@@ -1273,13 +1314,13 @@ static int sync_mode() {
 
 template <int K>
 static int launch_fill_k(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid,
-                         hipStream_t s) {
+                         int pass, hipStream_t s) {
   if (sync_mode() == 1)
     hipLaunchKernelGGL((fill_kernel<K, kFillThreads, 1>), dim3(grid), dim3(kFillThreads), 0, s,
-                       jd, ctrl, order);
+                       jd, ctrl, order, pass);
   else
     hipLaunchKernelGGL((fill_kernel<K, kFillThreads, 2>), dim3(grid), dim3(kFillThreads), 0, s,
-                       jd, ctrl, order);
+                       jd, ctrl, order, pass);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1321,8 +1362,9 @@ static int launch_export_k(const JobDev &jd, const Ctrl *ctrl, uint8_t *out, int
     default: return -1;                            \
   }
 
-int launch_fill(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, hipStream_t s) {
-  MSA_DISPATCH_K(jd.k, launch_fill_k, jd, ctrl, order, grid, s);
+int launch_fill(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, int pass,
+                hipStream_t s) {
+  MSA_DISPATCH_K(jd.k, launch_fill_k, jd, ctrl, order, grid, pass, s);
 }
 
 int launch_traceback(const JobDev &jd, Ctrl *ctrl, hipStream_t s) {

@@ -89,6 +89,27 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
   q.off_dir = o;
   if (!mul_ok(q.ntiles, q.dbs, lim)) return MSA_ENOMEM;
   o = align256(o + q.ntiles * q.dbs);
+  q.prunable = k >= kPruneMinK && k <= kPruneMaxK;
+  for (int i = 0; i < k; ++i) q.prunable = q.prunable && q.n[i] < kPruneMaxLen;
+  if (q.prunable) {
+    int64_t tab = 0, bm = 0;
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j) {
+        const int p = q.npairs++;
+        q.pi[p] = i;
+        q.pj[p] = j;
+        q.tab_off[p] = tab;
+        tab += 2 * ((int64_t)q.n[i] + 1) * ((int64_t)q.n[j] + 1);
+        q.bm_off[p] = bm;
+        bm += (int64_t)q.P[i] * q.P[j];
+      }
+    q.nblocks = (int32_t)((q.ntiles + kSelBlock - 1) / kSelBlock);
+    q.off_ptab = o;   o = align256(o + tab * 4);
+    q.off_pbm = o;    o = align256(o + bm * 4);
+    q.off_keep = o;   o = align256(o + q.ntiles);
+    q.off_korder = o; o = align256(o + q.ntiles * 4);
+    q.off_bcnt = o;   o = align256(o + (int64_t)q.nblocks * 4);
+  }
   q.bytes = o;
   *p = q;
   return MSA_OK;
@@ -182,6 +203,43 @@ void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd) {
   jd->dir = reinterpret_cast<uint8_t *>(ws + p.off_dir);
   jd->flags = reinterpret_cast<int32_t *>(ws + p.off_flags);
   jd->path = reinterpret_cast<uint8_t *>(ws + p.off_path);
+}
+
+}  // namespace msa
+
+namespace msa {
+
+void fill_prunedev(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score,
+                   PruneDev *pd) {
+  memset(pd, 0, sizeof(*pd));
+  pd->k = p.k;
+  pd->npairs = p.npairs;
+  pd->T = p.T;
+  pd->ntiles = (int32_t)p.ntiles;
+  int32_t off = 0;
+  for (int i = 0; i < p.k; ++i) {
+    pd->n[i] = p.n[i];
+    pd->P[i] = p.P[i];
+    pd->tstride[i] = p.tstride[i];
+    pd->seq_off[i] = off;
+    off += p.n[i];
+  }
+  for (int q = 0; q < p.npairs; ++q) {
+    pd->pi[q] = p.pi[q];
+    pd->pj[q] = p.pj[q];
+    pd->tab_off[q] = p.tab_off[q];
+    pd->bm_off[q] = p.bm_off[q];
+  }
+  pd->nblocks = p.nblocks;
+  pd->seqs = d_seqs;
+  pd->sub = reinterpret_cast<const int8_t *>(ws + p.off_sub);
+  pd->tabs = reinterpret_cast<int32_t *>(ws + p.off_ptab);
+  pd->bm = reinterpret_cast<int32_t *>(ws + p.off_pbm);
+  pd->keep = reinterpret_cast<uint8_t *>(ws + p.off_keep);
+  pd->order = reinterpret_cast<const int32_t *>(ws + p.off_order);
+  pd->korder = reinterpret_cast<int32_t *>(ws + p.off_korder);
+  pd->bcnt = reinterpret_cast<int32_t *>(ws + p.off_bcnt);
+  pd->score = d_score;
 }
 
 }  // namespace msa

@@ -29,6 +29,14 @@ struct Plan {
   int64_t off_ctrl = 0, off_sub = 0, off_order = 0, off_flags = 0, off_path = 0,
           off_faces = 0, off_dir = 0, bytes = 0;
   int64_t max_wave = 0;      // tiles in the widest computation wave
+  // pruned mode (3 <= k <= 6, every n_i < kPruneMaxLen): pairwise tables,
+  // block maxima, keep flags, the kept-tile queue and selection block counts
+  bool prunable = false;
+  int npairs = 0;
+  int32_t pi[kMaxPairs] = {}, pj[kMaxPairs] = {};
+  int64_t tab_off[kMaxPairs] = {}, bm_off[kMaxPairs] = {};  // int32 elements
+  int32_t nblocks = 0;
+  int64_t off_ptab = 0, off_pbm = 0, off_keep = 0, off_korder = 0, off_bcnt = 0;
 };
 
 constexpr int64_t kSubBytes = 255 * 255;
@@ -50,5 +58,9 @@ int score_bounds(const int32_t *lens, int32_t k, const int8_t *submat, int32_t a
 
 // Device descriptor for a plan placed at workspace base `ws`.
 void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd);
+
+// Pruning descriptor for a prunable plan at workspace base `ws`.
+void fill_prunedev(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score,
+                   PruneDev *pd);
 
 }  // namespace msa

@@ -3,7 +3,11 @@
 
 #include <string.h>
 
+#include <stdlib.h>
+
+#include <algorithm>
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/msa_dp.h"
@@ -12,6 +16,9 @@ namespace msa {
 
 namespace {
 std::mutex g_mu;
+// Mode flags of each prepared workspace (by device address), so that a launch
+// knows its kernel sequence without reading the device control block.
+std::unordered_map<uintptr_t, int32_t> g_ws_flags;
 int g_cu[64] = {};
 int g_occ[64][kMaxK + 1] = {};
 }  // namespace
@@ -28,6 +35,12 @@ int device_cu_count() {
     g_cu[dev] = n;
   }
   return g_cu[dev];
+}
+
+int32_t workspace_flags(const char *ws) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws_flags.find((uintptr_t)ws);
+  return it == g_ws_flags.end() ? 0 : it->second;
 }
 
 static int occupancy(int k) {
@@ -50,6 +63,13 @@ int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, 
   ctrl.gap = gap;
   ctrl.flags = flags;
   ctrl.best = INT64_MIN;
+  // pruned mode: the closed-form score floor and the first threshold's margin
+  int64_t lo = 0, hi = 0;
+  if (score_bounds(p.n, p.k, submat, alpha, gap, &lo, &hi) != 0) return MSA_EINVAL;
+  ctrl.lo = lo;
+  int cmax = gap < 0 ? -gap : gap;
+  for (int x = 0; x < alpha * alpha; ++x) cmax = std::max(cmax, std::abs((int)submat[x]));
+  ctrl.prune_c = (int64_t)(p.k * (p.k - 1) / 2) * cmax;
   bool ok = true;
   ok = ok && hipMemcpyAsync(ws + p.off_ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, s) ==
                  hipSuccess;
@@ -59,6 +79,10 @@ int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, 
                             hipMemcpyHostToDevice, s) == hipSuccess;
   ok = ok && hipMemsetAsync(ws + p.off_flags, 0, (size_t)p.ntiles * 4, s) == hipSuccess;
   ok = ok && hipStreamSynchronize(s) == hipSuccess;
+  if (ok) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_ws_flags[(uintptr_t)ws] = flags;
+  }
   return ok ? MSA_OK : MSA_EDEVICE;
 }
 
@@ -88,6 +112,27 @@ static int fill_grid(const Plan &p) {
   return (int)grid;
 }
 
+// The fill of a prepared workspace: one launch, or in pruned mode (the mode
+// is known to the host from the plan and flags cached at set-up) the bound,
+// selection and two-pass sequence of msa_prune.hip.
+static int run_fill(const Plan &p, char *ws, JobDev &jd, hipStream_t s) {
+  Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
+  const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
+  const int grid = fill_grid(p);
+  if (!(workspace_flags(ws) & kPrune)) return launch_fill(jd, ctrl, order, grid, 0, s);
+  PruneDev pd;
+  fill_prunedev(p, ws, jd.seqs, jd.score_out, &pd);
+  jd.keep = pd.keep;
+  const int32_t *korder = pd.korder;
+  if (launch_prune_bounds(pd, ctrl, s) != 0) return -1;
+  for (int pass = 1; pass <= 2; ++pass) {
+    if (launch_prune_select(pd, ctrl, pass, s) != 0) return -1;
+    if (launch_fill(jd, ctrl, korder, grid, pass, s) != 0) return -1;
+    if (pass == 1 && launch_prune_check(pd, ctrl, s) != 0) return -1;
+  }
+  return 0;
+}
+
 int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, uint8_t *d_aln,
               int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,
               int which) {
@@ -103,8 +148,7 @@ int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, 
   jd.trace = g_trace_buf;
 #endif
   Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
-  const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
-  if ((which & 1) && launch_fill(jd, ctrl, order, fill_grid(p), s) != 0) return MSA_EDEVICE;
+  if ((which & 1) && run_fill(p, ws, jd, s) != 0) return MSA_EDEVICE;
   if ((which & 2) && launch_traceback(jd, ctrl, s) != 0) return MSA_EDEVICE;
   return MSA_OK;
 }
@@ -119,8 +163,7 @@ int run_coopt(const Plan &p, char *ws, const uint8_t *d_seqs, int32_t max_paths,
   jd.aln_cap = aln_cap;
   jd.status_out = d_status;
   Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
-  const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
-  if (launch_fill(jd, ctrl, order, fill_grid(p), s) != 0) return MSA_EDEVICE;
+  if (run_fill(p, ws, jd, s) != 0) return MSA_EDEVICE;
   if (launch_coopt(jd, ctrl, max_paths, d_aln, d_aln_len, d_npaths, s) != 0) return MSA_EDEVICE;
   return MSA_OK;
 }
@@ -130,6 +173,24 @@ int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s) {
   fill_jobdev(p, ws, 0, 0, &jd);
   const Ctrl *ctrl = reinterpret_cast<const Ctrl *>(ws + p.off_ctrl);
   return launch_export(jd, ctrl, out, p.ncell, s) == 0 ? MSA_OK : MSA_EDEVICE;
+}
+
+}  // namespace msa
+
+namespace msa {
+
+int export_prune(const Plan &p, char *ws, uint8_t *keep_out, int64_t *info_out,
+                 hipStream_t s) {
+  if (!p.prunable || !(workspace_flags(ws) & kPrune)) return MSA_EINVAL;
+  const Ctrl *ctrl = reinterpret_cast<const Ctrl *>(ws + p.off_ctrl);
+  bool ok = true;
+  if (keep_out)
+    ok = ok && hipMemcpyAsync(keep_out, ws + p.off_keep, (size_t)p.ntiles,
+                              hipMemcpyDeviceToDevice, s) == hipSuccess;
+  if (info_out)  // prune_U, prune_L, prune_kept, prune_passes are contiguous
+    ok = ok && hipMemcpyAsync(info_out, &ctrl->prune_U, 4 * sizeof(int64_t),
+                              hipMemcpyDeviceToDevice, s) == hipSuccess;
+  return ok ? MSA_OK : MSA_EDEVICE;
 }
 
 }  // namespace msa

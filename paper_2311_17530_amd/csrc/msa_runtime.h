@@ -8,13 +8,19 @@
 namespace msa {
 
 // kernels (msa_kernels.hip)
-int launch_fill(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, hipStream_t s);
+// pass: 0 plain; 1, 2 the passes of the pruned mode (2 runs only after a miss)
+int launch_fill(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, int pass,
+                hipStream_t s);
 int launch_traceback(const JobDev &jd, Ctrl *ctrl, hipStream_t s);
 int launch_export(const JobDev &jd, const Ctrl *ctrl, uint8_t *out, int64_t ncell,
                   hipStream_t s);
 int launch_coopt(const JobDev &jd, Ctrl *ctrl, int32_t max_paths, uint8_t *aln_out,
                  int64_t *len_out, int32_t *npaths_out, hipStream_t s);
 int fill_occupancy(int k);
+// pruning kernels (msa_prune.hip)
+int launch_prune_bounds(const PruneDev &pd, Ctrl *ctrl, hipStream_t s);
+int launch_prune_select(const PruneDev &pd, Ctrl *ctrl, int pass, hipStream_t s);
+int launch_prune_check(const PruneDev &pd, Ctrl *ctrl, hipStream_t s);
 int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_jtiles,
                  int32_t *qjob, int32_t *qtile, int64_t total, int32_t *flags, Ctrl *ctrl,
                  int grid, hipStream_t s);
@@ -22,6 +28,8 @@ int batch_occupancy(int kclass);
 
 // runtime (msa_runtime.cpp)
 int device_cu_count();
+// mode flags given to prepare_workspace for the workspace at `ws` (0 if none)
+int32_t workspace_flags(const char *ws);
 int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, int gap,
                       int32_t flags, hipStream_t s);
 // which: 1 = fill only, 2 = traceback only, 3 = both
@@ -29,6 +37,10 @@ int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, 
               int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,
               int which = 3);
 int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s);
+// pruned mode: keep flags of the last pass (ntiles bytes, row-major tile
+// index) and {U, threshold, tiles kept, passes} of the last fill
+int export_prune(const Plan &p, char *ws, uint8_t *keep_out, int64_t *info_out,
+                 hipStream_t s);
 // fill, then up to max_paths co-optimal alignments (workspace prepared with
 // the co-optimal flag)
 int run_coopt(const Plan &p, char *ws, const uint8_t *d_seqs, int32_t max_paths, int64_t *d_score,

@@ -181,3 +181,34 @@ def _align_ex(seqs, sub, gap, flags):
                                    ctypes.byref(alen))
     if rc != msa.MSA_OK:
         raise msa.MsaError(rc, "msa_dp_align_ex")
+
+
+def test_prune_limits_rejected_before_device():
+    # pruned mode: 3 <= k <= 6, lengths < 16384, not with end-gap-free
+    sub, gap = dna_scoring()
+    a = np.array([0, 1, 2], np.uint8)
+    for seqs in ([a, a], [a] * 7):
+        with pytest.raises(msa.MsaError) as e:
+            msa.align(seqs, sub, gap, prune=True)
+        assert e.value.status == msa.MSA_EINVAL
+    with pytest.raises(msa.MsaError) as e:
+        msa.align([np.zeros(16384, np.uint8), a, a], sub, gap, prune=True)
+    assert e.value.status == msa.MSA_ERANGE
+    with pytest.raises(msa.MsaError) as e:
+        _align_ex([a] * 3, sub, gap, msa.MSA_PRUNE | msa.MSA_END_GAPS_FREE)
+    assert e.value.status == msa.MSA_EINVAL
+
+
+def test_prune_workspace_holds_pair_tables():
+    # the pruned mode's pairwise tables and queue live in the workspace of
+    # every shape it accepts: two int32 tables per pair plus per-tile data
+    T = msa.tile_edge(3)
+    lens = [40, 33, 47]
+    P, _ = msa.tile_grid(lens, T)
+    ntiles = int(np.prod(P))
+    pairs = [(0, 1), (0, 2), (1, 2)]
+    extra = sum(2 * (lens[i] + 1) * (lens[j] + 1) * 4 for i, j in pairs)
+    extra += sum(P[i] * P[j] * 4 for i, j in pairs) + ntiles * 5
+    base = msa.workspace_bytes([40, 33])  # k = 2: no pruning area
+    assert msa.workspace_bytes(lens) >= extra + ntiles * ((T ** 3 + 15) // 16 * 16)
+    assert base > 0
