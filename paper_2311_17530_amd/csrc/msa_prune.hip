@@ -32,7 +32,6 @@ namespace {
 enum { ST_OK = 0 };
 
 constexpr int kRB = 16;           // rows per lane in one band (band = 1024 rows)
-constexpr int kPairSubLds = 64;   // substitution matrix in LDS up to this alphabet
 // largest number of tiles along a dimension (T >= 3 for k <= 6)
 constexpr int kMaxTilesPerDim = 1 + (kPruneMaxLen - 1 + 2) / 3;
 
@@ -48,10 +47,19 @@ constexpr int kMaxTilesPerDim = 1 + (kPruneMaxLen - 1 + 2) / 3;
 // One wave per table, rows in bands of 64 * RB: lane l holds rows
 // base + l*RB .. base + l*RB + RB - 1 and handles column b = s - l at step s
 // (an anti-diagonal pipeline).  The value above a lane's first row arrives
-// from the lane below by a shuffle, together with the column's residue; lane
-// 0 reads the band's upper boundary (the previous band's last row) from the
-// table, 64 columns per load.
+// from the lane below by a one-lane wave shift (DPP), together with the
+// column's residue; lane 0 reads the band's upper boundary (the previous
+// band's last row) from the table, 64 columns per load.  The substitution
+// matrix sits in LDS, so the step loop issues no global load but those
+// 64-column refills (on gfx9 a wait for a load also waits for every earlier
+// store, and each step stores its cells).
 // ---------------------------------------------------------------------------
+
+// Lane l receives lane l - 1's value, lane 0 receives `first` (DPP wave_shr:1).
+__device__ __forceinline__ int shift_up1(int v, int first) {
+  return __builtin_amdgcn_update_dpp(first, v, 0x138, 0xF, 0xF, false);
+}
+
 __global__ __launch_bounds__(64) void pair_table_kernel(PruneDev pd, const Ctrl *ctrl) {
   const int p = blockIdx.x >> 1;
   const int dir = blockIdx.x & 1;
@@ -68,12 +76,9 @@ __global__ __launch_bounds__(64) void pair_table_kernel(PruneDev pd, const Ctrl 
   auto at = [&](int a, int b) -> int64_t {
     return dir ? (int64_t)(nj - b) * rows + (ni - a) : (int64_t)b * rows + a;
   };
-  __shared__ int8_t sub[kPairSubLds * kPairSubLds];
-  const bool subl = alpha <= kPairSubLds;
+  __shared__ int8_t sub[255 * 255];
   const int lane = threadIdx.x;
-  if (subl)
-    for (int x = lane; x < alpha * alpha; x += 64)
-      sub[(x / alpha) * kPairSubLds + x % alpha] = pd.sub[x];
+  for (int x = lane; x < alpha * alpha; x += 64) sub[x] = pd.sub[x];
   __syncthreads();
 
   const int RB = min(kRB, (rows + 63) / 64);
@@ -86,31 +91,49 @@ __global__ __launch_bounds__(64) void pair_table_kernel(PruneDev pd, const Ctrl 
       const int a = a0 + r;
       const bool in = r < RB && a >= 1 && a < rows;
       // codes >= alpha are reported by the fill; clamped here to stay in the matrix
-      x[r] = in ? min((int)(dir ? si[ni - a] : si[a - 1]), alpha - 1) : 0;
+      x[r] = (in ? min((int)(dir ? si[ni - a] : si[a - 1]), alpha - 1) : 0) * alpha;
       cur[r] = 0;
     }
     int32_t bot = 0;    // this lane's last row at the previous step
     int32_t diag0 = 0;  // the value above the first row, previous column
     int yv = 0;         // residue of this lane's column
-    int ychunk = 0, bchunk = 0;
-    for (int s = 0; s < cols + 63; ++s) {
+    // lane 0's columns c0 .. c0 + 63: residue codes and the band's upper
+    // boundary, loaded one chunk ahead so that only the refill waits
+    auto load_y = [&](int c0) -> int {
+      const int bb = c0 + lane;
+      return (bb >= 1 && bb < cols) ? (int)(dir ? sj[nj - bb] : sj[bb - 1]) : 0;
+    };
+    auto load_b = [&](int c0) -> int32_t {
+      const int bb = c0 + lane;
+      return (bb < cols && base > 0) ? tab[at(base - 1, bb < cols ? bb : 0)] : 0;
+    };
+    int ynext = load_y(0), bnext = load_b(0);
+    for (int c0 = 0; c0 < cols + 63; c0 += 64) {
+     // chunks of 64 steps: the step loop itself issues no load
+     const int ychunk = ynext;
+     const int32_t bchunk = bnext;
+     ynext = load_y(c0 + 64);
+     bnext = load_b(c0 + 64);
+     const int send = min(c0 + 64, cols + 63);
+     for (int s = c0; s < send; ++s) {
       const int b = s - lane;
-      const int32_t above = __shfl_up(bot, 1, 64);
-      const int yin = __shfl_up(yv, 1, 64);
-      if ((s & 63) == 0) {
-        // lane 0's next 64 columns: residues and the band's upper boundary
-        const int bb = s + lane;
-        const bool okb = bb < cols;
-        ychunk = (okb && bb >= 1) ? min((int)(dir ? sj[nj - bb] : sj[bb - 1]), alpha - 1) : 0;
-        bchunk = (okb && base > 0) ? tab[at(base - 1, okb ? bb : 0)] : 0;
-      }
-      const int y0 = __builtin_amdgcn_readlane(ychunk, s & 63);
+      const int32_t above = shift_up1(bot, 0);
+      const int yin = shift_up1(yv, 0);
+      // codes >= alpha are reported by the fill; clamped here to stay in the matrix
+      const int y0 = min(__builtin_amdgcn_readlane(ychunk, s & 63), alpha - 1);
       const int32_t b0 = __builtin_amdgcn_readlane(bchunk, s & 63);
       yv = lane == 0 ? y0 : yin;
       int32_t up = lane == 0 ? b0 : above;  // (a0 - 1, b)
       if (b >= 0 && b < cols) {
         int32_t dg = diag0;                 // (a0 - 1, b - 1)
         diag0 = up;
+        // this lane's cells of column b: ascending rows (prefix table) or
+        // descending (mirrored suffix table)
+        int32_t *colp = tab + at(a0, b);
+        const int rstep = dir ? -1 : 1;
+        int sc[kRB];
+#pragma unroll
+        for (int r = 0; r < kRB; ++r) sc[r] = (int)sub[x[r] + yv];
 #pragma unroll
         for (int r = 0; r < kRB; ++r) {
           const int a = a0 + r;
@@ -121,18 +144,17 @@ __global__ __launch_bounds__(64) void pair_table_kernel(PruneDev pd, const Ctrl 
             } else if (b == 0) {
               v = a * gap;
             } else {
-              const int sc = subl ? (int)sub[x[r] * kPairSubLds + yv]
-                                  : (int)pd.sub[x[r] * alpha + yv];
-              v = max(max(up, cur[r]) + gap, dg + sc);
+              v = max(max(up, cur[r]) + gap, dg + sc[r]);
             }
             dg = cur[r];  // (a, b - 1): the diagonal of (a + 1, b)
             cur[r] = v;
             up = v;
             bot = v;
-            tab[at(a, b)] = v;
+            colp[r * rstep] = v;
           }
         }
       }
+     }
     }
     // the band's last row is read back by the next band
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
