@@ -52,8 +52,8 @@ struct JobDev {
   // batched path only
   int32_t *jstatus;           // per-job status (bad residue code)
   const int32_t *wcnt;        // (k+1) x nwaves: tuples (c_d..c_{k-1}) summing to s
-  const int32_t *wstart;      // nwaves + 1: tiles in the waves before w
-  int64_t qbase;              // first queue slot of this job
+  const int64_t *wbase;       // nwaves: queue slot of this job's first tile of wave w
+  int64_t qbase;              // first tile of this job in the launch's tile numbering
 };
 
 // Control block of one persistent launch (in device memory).

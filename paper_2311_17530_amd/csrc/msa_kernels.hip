@@ -1155,10 +1155,10 @@ __global__ void export_dirs_kernel(JobDev jd, const Ctrl *ctrl, uint8_t *out, in
 // Batched path: many jobs (uneven k and lengths) in one persistent launch.
 // ---------------------------------------------------------------------------
 
-// Queue construction: slot of tile t of job j = qbase + (tiles of the waves
-// before t's wave) + (rank of t among its wave's tiles in lexicographic
-// order).  Every job's tiles therefore appear in wave order, which makes the
-// concatenated queue a topological order of all dependencies.
+// Queue construction: slot of tile t of job j = wbase_j[w] (where the host
+// placed job j's share of wave w in the wave-major queue) + (rank of t among
+// its wave's tiles in lexicographic order).  Every job's tiles appear in wave
+// order, which makes the queue a topological order of all dependencies.
 __global__ void batch_queue_kernel(const JobDev *__restrict__ jobs, int njobs,
                                    const int64_t *__restrict__ jtiles, int32_t *qjob,
                                    int32_t *qtile) {
@@ -1185,7 +1185,7 @@ __global__ void batch_queue_kernel(const JobDev *__restrict__ jobs, int njobs,
         if (s - cc >= 0) rank += jd.wcnt[(d + 1) * jd.nwaves + (s - cc)];
       s -= c[d];
     }
-    const int64_t pos = jd.qbase + jd.wstart[w] + rank;
+    const int64_t pos = jd.wbase[w] + rank;
     qjob[pos] = lo;
     qtile[pos] = t;
   }

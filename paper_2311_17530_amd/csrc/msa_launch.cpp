@@ -45,7 +45,7 @@ int sizes_of(const msa_job &j, JobSizes *s) {
   s->nw = p.nwaves;
   s->small = a256(std::max<int64_t>(p.total_len, 1)) +        // sequences
              a256((int64_t)(j.k + 1) * p.nwaves * 4) +        // wave counts
-             a256((int64_t)(p.nwaves + 1) * 4) +              // wave starts
+             a256((int64_t)p.nwaves * 8) +                    // wave queue slots
              256;                                             // job status
   s->big = a256(std::max<int64_t>(p.total_len, 1)) +          // traceback path
            a256(std::max<int64_t>(p.face_elems * 4, 256)) +   // face planes
@@ -197,6 +197,8 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   int64_t *jt = reinterpret_cast<int64_t *>(h + off_jt);
   jt[0] = 0;
   meta_.assign(nj, Meta());
+  std::vector<const int32_t *> wave_cnt(nj);
+  std::vector<int64_t *> wave_base(nj);
   JobDev *jd_all = reinterpret_cast<JobDev *>(h + off_jobs);
   for (int i = 0; i < nj; ++i) {
     const msa_job &j = *jobs[i];
@@ -227,16 +229,15 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
       }
     so += a256((int64_t)(j.k + 1) * nw * 4);
     const int64_t o_wst = so;
-    int32_t *ws = reinterpret_cast<int32_t *>(h + so);
-    ws[0] = 0;
-    for (int w = 0; w < nw; ++w) ws[w + 1] = ws[w] + wc[w];
-    so += a256((int64_t)(nw + 1) * 4);
+    wave_cnt[i] = wc;  // row 0: tiles per wave
+    wave_base[i] = reinterpret_cast<int64_t *>(h + so);
+    so += a256((int64_t)nw * 8);
     const int64_t o_jst = so;
     // device pointers
     jd.seqs = reinterpret_cast<const uint8_t *>(d_ + o_seq);
     jd.sub = reinterpret_cast<const int8_t *>(d_ + sub_off[i]);
     jd.wcnt = reinterpret_cast<const int32_t *>(d_ + o_wcnt);
-    jd.wstart = reinterpret_cast<const int32_t *>(d_ + o_wst);
+    jd.wbase = reinterpret_cast<const int64_t *>(d_ + o_wst);
     jd.jstatus = reinterpret_cast<int32_t *>(d_ + o_jst);
     jd.qbase = jt[i];
     jd.flags = reinterpret_cast<int32_t *>(d_ + off_flags) + jt[i];
@@ -256,6 +257,30 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
     meta_[i].k = j.k;
     meta_[i].cap = sz[i].cap;
     meta_[i].aln_off = job_out[i] - off_out;
+  }
+
+  // Queue order: wave-major across jobs (every job's wave-0 tiles, then
+  // every job's wave-1 tiles, ...), so the persistent workgroups work on all
+  // jobs' wavefronts at once instead of waiting on one job's dependency chain
+  // at a time.  Each job's tiles stay in wave order, so the queue is still a
+  // topological order of every dependency.
+  {
+    int wmax = 0;
+    for (int i = 0; i < nj; ++i) wmax = std::max(wmax, sz[i].p.nwaves);
+    std::vector<int64_t> slot(wmax, 0);  // next free slot of wave w
+    std::vector<int64_t> tot(wmax, 0);
+    for (int i = 0; i < nj; ++i)
+      for (int w = 0; w < sz[i].p.nwaves; ++w) tot[w] += wave_cnt[i][w];
+    int64_t acc = 0;
+    for (int w = 0; w < wmax; ++w) {
+      slot[w] = acc;
+      acc += tot[w];
+    }
+    for (int i = 0; i < nj; ++i)
+      for (int w = 0; w < sz[i].p.nwaves; ++w) {
+        wave_base[i][w] = slot[w];
+        slot[w] += wave_cnt[i][w];
+      }
   }
 
   // ---- enqueue ----
