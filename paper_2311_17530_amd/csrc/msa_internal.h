@@ -48,6 +48,8 @@ struct JobDev {
   int64_t *aln_len_out;
   int32_t *status_out;
   const uint8_t *keep;        // pruned mode: per-tile keep flags (else null)
+  const int32_t *corder;      // column schedule: first tile of each column, in order
+  int32_t ncols;              // columns along dimension 0 (0: tile queue instead)
   int64_t *trace;             // optional per-tile phase timestamps (debug builds)
   // batched path only
   int32_t *jstatus;           // per-job status (bad residue code)

@@ -173,11 +173,14 @@ __device__ inline void shift_in(uint32_t (&d)[NR], uint32_t byte) {
 // prune: pruned mode (plain path, k <= 6): only kept tiles (jd.keep) run; a
 // tile waits for every kept lower-neighbour tile and takes the halo cells of
 // the others as -infinity.
+// own0: the tile's predecessor along dimension 0 was this workgroup's previous
+// tile (column schedule), so its last layer is still in LDS: that halo face is
+// copied inside LDS instead of loaded, and its flag is not polled.
 template <int K, int NT, int SYNC>
 __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int epoch,
                              Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm, bool egf = false,
                              int64_t *best_key = nullptr, bool coopt = false,
-                             bool prune = false) {
+                             bool prune = false, bool own0 = false) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int E = C::E;
@@ -288,7 +291,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     } else {
 #pragma unroll
       for (int i = 0; i < K; ++i) {
-        if (tid == i && c[i] > 0) {
+        if (tid == i && c[i] > 0 && !(own0 && i == 0)) {
           need = true;
           f = jd.flags + (tile - jd.tstride[i]);
         }
@@ -322,6 +325,20 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
   // ---- halo: layer l_i = 0 along each dimension ----
   // Loads first, LDS stores after: for small k every face load of every
   // dimension is in flight at once (one memory round trip per tile).
+  if (own0) {
+    // layer l_0 = 0 is the previous tile's last layer (l_0 = its extent)
+    const int e0 = c[0] - 1 == 0 ? 1 : T;
+    constexpr int cnt = ipow(E, K - 1);
+    for (int idx = tid; idx < cnt; idx += NT) {
+      int rem = idx, s = 0;
+#pragma unroll
+      for (int j = K - 1; j >= 1; --j) {
+        s += (rem % E) * C::sstride(j);
+        rem /= E;
+      }
+      sm.S[s] = sm.S[s + e0 * C::sstride(0)];
+    }
+  }
   {
     constexpr int cnt = ipow(E, K - 1);
     constexpr int IT = (cnt + NT - 1) / NT;
@@ -358,6 +375,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
               src |= (l == 0 ? 1 : 0) << j;
               foff += (int64_t)v * jd.fstride[i][j];
             }
+            valid = valid && !(own0 && i == 0);  // copied inside LDS above
             sidx[di][it] = valid ? s : -1;
             // a cell of a pruned tile was never computed: -infinity
             const bool take = valid && !neg && ((kbits >> (src & 63)) & 1) != 0;
@@ -729,7 +747,11 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
   const bool egf = (mode & kEndGapsFree) != 0;
   const bool coopt = (mode & kCoOptimal) != 0;
   const bool prune = (mode & kPrune) != 0;
-  const int nq = prune ? __builtin_amdgcn_readfirstlane(ctrl->nqueue) : jd.ntiles;
+  // column schedule (not in pruned mode): a workgroup takes a column of tiles
+  // along dimension 0 and computes it bottom up
+  const bool cols = !prune && jd.ncols > 0;
+  const int nq = prune ? __builtin_amdgcn_readfirstlane(ctrl->nqueue)
+                       : cols ? jd.ncols : jd.ntiles;
   load_tables<K, NT>(jd, alpha, sm);
   const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
@@ -748,8 +770,16 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
     const int qi = __builtin_amdgcn_readfirstlane(bcast);
     __syncthreads();
     if (qi >= nq) break;
-    process_tile<K, NT, SYNC>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]), epoch,
-                              ctrl, &ctrl->status, sm, egf, &ctrl->best, coopt, prune);
+    if (cols) {
+      const int base = __builtin_amdgcn_readfirstlane(jd.corder[qi]);
+      for (int c0 = 0; c0 < jd.P[0]; ++c0)
+        process_tile<K, NT, SYNC>(jd, alpha, gap, base + c0 * jd.tstride[0], epoch, ctrl,
+                                  &ctrl->status, sm, egf, &ctrl->best, coopt, false, c0 > 0);
+    } else {
+      process_tile<K, NT, SYNC>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]),
+                                epoch, ctrl, &ctrl->status, sm, egf, &ctrl->best, coopt,
+                                prune);
+    }
   }
 }
 

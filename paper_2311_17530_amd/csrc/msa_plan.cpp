@@ -80,6 +80,8 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
   q.off_ctrl = o;   o = align256(o + (int64_t)sizeof(Ctrl));
   q.off_sub = o;    o = align256(o + kSubBytes);
   q.off_order = o;  o = align256(o + q.ntiles * 4);
+  q.ncols = q.ntiles / q.P[0];
+  q.off_corder = o; o = align256(o + q.ncols * 4);
   q.off_flags = o;  o = align256(o + q.ntiles * 4);
   q.off_path = o;   o = align256(o + std::max<int64_t>(q.total_len, 1));
   q.off_faces = o;
@@ -126,6 +128,15 @@ void make_tile_order(const Plan &p, std::vector<int32_t> *order) {
   for (int w = 0; w < p.nwaves; ++w) count[w + 1] += count[w];
   order->assign(p.ntiles, 0);
   for (int64_t t = 0; t < p.ntiles; ++t) (*order)[count[wave(t)]++] = (int32_t)t;
+}
+
+void make_column_order(const Plan &p, std::vector<int32_t> *order) {
+  std::vector<int32_t> all;
+  make_tile_order(p, &all);
+  order->clear();
+  order->reserve(p.ncols);
+  for (int32_t t : all)
+    if (t / p.tstride[0] == 0) order->push_back(t);  // c_0 = 0: first tile of a column
 }
 
 int score_bounds(const int32_t *lens, int32_t k, const int8_t *submat, int32_t alpha,
@@ -202,6 +213,8 @@ void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd) {
   jd->faces = reinterpret_cast<int32_t *>(ws + p.off_faces);
   jd->dir = reinterpret_cast<uint8_t *>(ws + p.off_dir);
   jd->flags = reinterpret_cast<int32_t *>(ws + p.off_flags);
+  jd->corder = reinterpret_cast<const int32_t *>(ws + p.off_corder);
+  jd->ncols = (int32_t)p.ncols;
   jd->path = reinterpret_cast<uint8_t *>(ws + p.off_path);
 }
 

@@ -28,6 +28,7 @@ struct Plan {
   // workspace layout (byte offsets from the workspace base)
   int64_t off_ctrl = 0, off_sub = 0, off_order = 0, off_flags = 0, off_path = 0,
           off_faces = 0, off_dir = 0, bytes = 0;
+  int64_t ncols = 0, off_corder = 0;  // tile columns along dimension 0 and their order
   int64_t max_wave = 0;      // tiles in the widest computation wave
   // pruned mode (3 <= k <= 6, every n_i < kPruneMaxLen): pairwise tables,
   // block maxima, keep flags, the kept-tile queue and selection block counts
@@ -47,6 +48,10 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p);
 
 // Tiles ordered by computation wave (sum of tile coordinates).
 void make_tile_order(const Plan &p, std::vector<int32_t> *order);
+
+// Tile columns along dimension 0 (the tiles with equal c_1..c_{k-1}), given
+// by their c_0 = 0 tile, ordered by the wave of that tile.
+void make_column_order(const Plan &p, std::vector<int32_t> *order);
 
 // Validation of scoring inputs (matrix symmetric, alpha range) and the
 // device integer range check.  Returns 0 or a negative status.

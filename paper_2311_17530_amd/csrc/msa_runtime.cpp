@@ -77,6 +77,10 @@ int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, 
                             hipMemcpyHostToDevice, s) == hipSuccess;
   ok = ok && hipMemcpyAsync(ws + p.off_order, order.data(), order.size() * 4,
                             hipMemcpyHostToDevice, s) == hipSuccess;
+  std::vector<int32_t> corder;
+  make_column_order(p, &corder);
+  ok = ok && hipMemcpyAsync(ws + p.off_corder, corder.data(), corder.size() * 4,
+                            hipMemcpyHostToDevice, s) == hipSuccess;
   ok = ok && hipMemsetAsync(ws + p.off_flags, 0, (size_t)p.ntiles * 4, s) == hipSuccess;
   ok = ok && hipStreamSynchronize(s) == hipSuccess;
   if (ok) {
@@ -118,7 +122,14 @@ static int fill_grid(const Plan &p) {
 static int run_fill(const Plan &p, char *ws, JobDev &jd, hipStream_t s) {
   Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
   const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
-  const int grid = fill_grid(p);
+  int grid = fill_grid(p);
+  // MSA_COLUMNS=0 (tuning): the tile queue instead of the column schedule
+  static const int col_env = [] {
+    const char *e = getenv("MSA_COLUMNS");
+    return e ? atoi(e) : 1;
+  }();
+  if (!col_env) jd.ncols = 0;
+  if (jd.ncols > 0 && grid > jd.ncols) grid = jd.ncols;
   if (!(workspace_flags(ws) & kPrune)) return launch_fill(jd, ctrl, order, grid, 0, s);
   PruneDev pd;
   fill_prunedev(p, ws, jd.seqs, jd.score_out, &pd);
