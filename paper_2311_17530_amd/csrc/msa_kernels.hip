@@ -176,11 +176,13 @@ __device__ inline void shift_in(uint32_t (&d)[NR], uint32_t byte) {
 // own0: the tile's predecessor along dimension 0 was this workgroup's previous
 // tile (column schedule), so its last layer is still in LDS: that halo face is
 // copied inside LDS instead of loaded, and its flag is not polled.
+// cols: column schedule; no tile reads a dimension-0 face plane, so none is
+// exported.
 template <int K, int NT, int SYNC>
 __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int epoch,
                              Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm, bool egf = false,
                              int64_t *best_key = nullptr, bool coopt = false,
-                             bool prune = false, bool own0 = false) {
+                             bool prune = false, bool own0 = false, bool cols = false) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int E = C::E;
@@ -641,7 +643,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
 #pragma unroll
       for (int di = 0; di < DG; ++di) {
         const int i = i0 + di;
-        const bool has_succ = c[i] < jd.P[i] - 1;
+        const bool has_succ = c[i] < jd.P[i] - 1 && !(cols && i == 0);
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
           const int idx = tid + it * NT;
@@ -774,7 +776,8 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
       const int base = __builtin_amdgcn_readfirstlane(jd.corder[qi]);
       for (int c0 = 0; c0 < jd.P[0]; ++c0)
         process_tile<K, NT, SYNC>(jd, alpha, gap, base + c0 * jd.tstride[0], epoch, ctrl,
-                                  &ctrl->status, sm, egf, &ctrl->best, coopt, false, c0 > 0);
+                                  &ctrl->status, sm, egf, &ctrl->best, coopt, false, c0 > 0,
+                                  true);
     } else {
       process_tile<K, NT, SYNC>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]),
                                 epoch, ctrl, &ctrl->status, sm, egf, &ctrl->best, coopt,
