@@ -1188,32 +1188,34 @@ __global__ void export_dirs_kernel(JobDev jd, const Ctrl *ctrl, uint8_t *out, in
 // Batched path: many jobs (uneven k and lengths) in one persistent launch.
 // ---------------------------------------------------------------------------
 
-// Queue construction: slot of tile t of job j = wbase_j[w] (where the host
-// placed job j's share of wave w in the wave-major queue) + (rank of t among
-// its wave's tiles in lexicographic order).  Every job's tiles appear in wave
-// order, which makes the queue a topological order of all dependencies.
+// Queue construction over tile columns along dimension 0: column t of job j
+// (its c_0 = 0 tile, t = sum_{d>=1} c_d * tstride[d]) goes to slot wbase_j[w]
+// (where the host placed job j's columns starting in wave w = sum c_d) + its
+// rank among those columns in lexicographic order of (c_1..c_{k-1}).  Every
+// job's columns appear in the order of their first tile's wave, which makes
+// the queue a topological order of all dependencies.
 __global__ void batch_queue_kernel(const JobDev *__restrict__ jobs, int njobs,
-                                   const int64_t *__restrict__ jtiles, int32_t *qjob,
+                                   const int64_t *__restrict__ jcols, int32_t *qjob,
                                    int32_t *qtile) {
-  const int64_t total = jtiles[njobs];
+  const int64_t total = jcols[njobs];
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    int lo = 0, hi = njobs;  // jtiles[lo] <= g < jtiles[hi]
+    int lo = 0, hi = njobs;  // jcols[lo] <= g < jcols[hi]
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (jtiles[mid] <= g) lo = mid; else hi = mid;
+      if (jcols[mid] <= g) lo = mid; else hi = mid;
     }
     const JobDev &jd = jobs[lo];
-    const int t = (int)(g - jtiles[lo]);
+    const int t = (int)(g - jcols[lo]);
     int c[kMaxK];
     int w = 0;
-    for (int d = 0; d < jd.k; ++d) {
+    for (int d = 1; d < jd.k; ++d) {
       c[d] = (t / jd.tstride[d]) % jd.P[d];
       w += c[d];
     }
     int64_t rank = 0;
     int s = w;
-    for (int d = 0; d < jd.k - 1; ++d) {
+    for (int d = 1; d < jd.k - 1; ++d) {
       for (int cc = 0; cc < c[d]; ++cc)
         if (s - cc >= 0) rank += jd.wcnt[(d + 1) * jd.nwaves + (s - cc)];
       s -= c[d];
@@ -1240,9 +1242,11 @@ constexpr size_t batch_smem_bytes() {
 
 // One tile of job `jd` with K = k; reloads the per-k cell table and the
 // job's substitution matrix into LDS when they differ from the cached ones.
+// The column of tiles base + c_0 * tstride[0], bottom up (see process_tile's
+// own0 and cols).
 template <int K, int NT>
-__device__ void batch_tile(const JobDev &jd, int tile, int epoch, Ctrl *ctrl, void *smraw,
-                           int &cur_k, const int8_t *&cur_sub) {
+__device__ void batch_column(const JobDev &jd, int base, int epoch, Ctrl *ctrl, void *smraw,
+                             int &cur_k, const int8_t *&cur_sub) {
   Smem<K> &sm = *reinterpret_cast<Smem<K> *>(smraw);
   if (cur_k != K || cur_sub != jd.sub) {
     __syncthreads();
@@ -1251,7 +1255,9 @@ __device__ void batch_tile(const JobDev &jd, int tile, int epoch, Ctrl *ctrl, vo
     cur_k = K;
     cur_sub = jd.sub;
   }
-  process_tile<K, NT, 2>(jd, jd.alpha, jd.gap, tile, epoch, ctrl, jd.jstatus, sm);
+  for (int c0 = 0; c0 < jd.P[0]; ++c0)
+    process_tile<K, NT, 2>(jd, jd.alpha, jd.gap, base + c0 * jd.tstride[0], epoch, ctrl,
+                           jd.jstatus, sm, false, nullptr, false, false, c0 > 0, true);
 }
 
 template <int KLO, int KHI, int NT>
@@ -1278,13 +1284,13 @@ __global__ __launch_bounds__(NT) void batch_fill_kernel(const JobDev *__restrict
     const int tile = __builtin_amdgcn_readfirstlane(qtile[q]);
     const JobDev &jd = jobs[j];
     switch (jd.k) {
-      case 2: if constexpr (KLO <= 2 && 2 <= KHI) batch_tile<2, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 3: if constexpr (KLO <= 3 && 3 <= KHI) batch_tile<3, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 4: if constexpr (KLO <= 4 && 4 <= KHI) batch_tile<4, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 5: if constexpr (KLO <= 5 && 5 <= KHI) batch_tile<5, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 6: if constexpr (KLO <= 6 && 6 <= KHI) batch_tile<6, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 7: if constexpr (KLO <= 7 && 7 <= KHI) batch_tile<7, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 8: if constexpr (KLO <= 8 && 8 <= KHI) batch_tile<8, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 2: if constexpr (KLO <= 2 && 2 <= KHI) batch_column<2, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 3: if constexpr (KLO <= 3 && 3 <= KHI) batch_column<3, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 4: if constexpr (KLO <= 4 && 4 <= KHI) batch_column<4, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 5: if constexpr (KLO <= 5 && 5 <= KHI) batch_column<5, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 6: if constexpr (KLO <= 6 && 6 <= KHI) batch_column<6, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 7: if constexpr (KLO <= 7 && 7 <= KHI) batch_column<7, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 8: if constexpr (KLO <= 8 && 8 <= KHI) batch_column<8, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
       default: break;
     }
   }
@@ -1426,29 +1432,32 @@ namespace msa {
 constexpr int kBatchThreads = 256;
 
 template <int KLO, int KHI>
-static int launch_batch_k(const JobDev *d_jobs, int njobs, const int64_t *d_jtiles,
-                          int32_t *qjob, int32_t *qtile, int64_t total, int32_t *flags,
-                          Ctrl *ctrl, int grid, hipStream_t s) {
-  int64_t qb = (total + 255) / 256;
+static int launch_batch_k(const JobDev *d_jobs, int njobs, const int64_t *d_jcols,
+                          int32_t *qjob, int32_t *qtile, int64_t tiles, int64_t cols,
+                          int32_t *flags, Ctrl *ctrl, int grid, hipStream_t s) {
+  int64_t qb = (tiles + 255) / 256;
   if (qb > 8192) qb = 8192;
   if (qb < 1) qb = 1;
-  hipLaunchKernelGGL(batch_zero_kernel, dim3((unsigned)qb), dim3(256), 0, s, flags, total);
+  hipLaunchKernelGGL(batch_zero_kernel, dim3((unsigned)qb), dim3(256), 0, s, flags, tiles);
   hipLaunchKernelGGL(batch_queue_kernel, dim3((unsigned)qb), dim3(256), 0, s, d_jobs, njobs,
-                     d_jtiles, qjob, qtile);
+                     d_jcols, qjob, qtile);
+  if (grid > cols) grid = (int)(cols > 0 ? cols : 1);
   hipLaunchKernelGGL((batch_fill_kernel<KLO, KHI, kBatchThreads>), dim3(grid),
-                     dim3(kBatchThreads), 0, s, d_jobs, qjob, qtile, (int32_t)total, ctrl);
+                     dim3(kBatchThreads), 0, s, d_jobs, qjob, qtile, (int32_t)cols, ctrl);
   hipLaunchKernelGGL((batch_traceback_kernel<KLO, KHI>), dim3(njobs), dim3(64), 0, s, d_jobs,
                      njobs, ctrl);
   hipLaunchKernelGGL(batch_finish_kernel, dim3(1), dim3(64), 0, s, ctrl);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_jtiles,
-                 int32_t *qjob, int32_t *qtile, int64_t total, int32_t *flags, Ctrl *ctrl,
-                 int grid, hipStream_t s) {
+int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_jcols,
+                 int32_t *qjob, int32_t *qtile, int64_t tiles, int64_t cols, int32_t *flags,
+                 Ctrl *ctrl, int grid, hipStream_t s) {
   if (kclass == 0)
-    return launch_batch_k<2, 4>(d_jobs, njobs, d_jtiles, qjob, qtile, total, flags, ctrl, grid, s);
-  return launch_batch_k<5, 8>(d_jobs, njobs, d_jtiles, qjob, qtile, total, flags, ctrl, grid, s);
+    return launch_batch_k<2, 4>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
+                                grid, s);
+  return launch_batch_k<5, 8>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
+                              grid, s);
 }
 
 int batch_occupancy(int kclass) {

@@ -141,6 +141,7 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   const int64_t off_ctrl = o;  o += 256;
   const int64_t off_jobs = o;  o = a256(o + (int64_t)nj * sizeof(JobDev));
   const int64_t off_jt = o;    o = a256(o + (int64_t)(nj + 1) * 8);
+  const int64_t off_jc = o;    o = a256(o + (int64_t)(nj + 1) * 8);
   // substitution matrices, deduplicated by content
   std::map<std::string, int64_t> subs;
   std::vector<int64_t> sub_off(nj);
@@ -195,7 +196,9 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   for (auto &kv : subs)
     memcpy(h + kv.second, kv.first.data(), kv.first.size() - 1);
   int64_t *jt = reinterpret_cast<int64_t *>(h + off_jt);
+  int64_t *jc = reinterpret_cast<int64_t *>(h + off_jc);  // columns before job i
   jt[0] = 0;
+  jc[0] = 0;
   meta_.assign(nj, Meta());
   std::vector<const int32_t *> wave_cnt(nj);
   std::vector<int64_t *> wave_base(nj);
@@ -204,6 +207,7 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
     const msa_job &j = *jobs[i];
     const Plan &p = sz[i].p;
     jt[i + 1] = jt[i] + p.ntiles;
+    jc[i + 1] = jc[i] + p.ncols;
     JobDev jd;
     fill_jobdev(p, nullptr, j.alpha, j.gap, &jd);
     // small region of this job
@@ -229,7 +233,7 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
       }
     so += a256((int64_t)(j.k + 1) * nw * 4);
     const int64_t o_wst = so;
-    wave_cnt[i] = wc;  // row 0: tiles per wave
+    wave_cnt[i] = wc + nw;  // row 1: columns by the wave of their first tile
     wave_base[i] = reinterpret_cast<int64_t *>(h + so);
     so += a256((int64_t)nw * 8);
     const int64_t o_jst = so;
@@ -259,11 +263,13 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
     meta_[i].aln_off = job_out[i] - off_out;
   }
 
-  // Queue order: wave-major across jobs (every job's wave-0 tiles, then
-  // every job's wave-1 tiles, ...), so the persistent workgroups work on all
-  // jobs' wavefronts at once instead of waiting on one job's dependency chain
-  // at a time.  Each job's tiles stay in wave order, so the queue is still a
-  // topological order of every dependency.
+  // The queue holds tile columns along dimension 0 (a workgroup computes a
+  // column bottom up, as in the plain fill) in wave-major order across jobs:
+  // every job's columns starting in wave 0, then every job's columns starting
+  // in wave 1, ...  The persistent workgroups so work on all jobs' wavefronts
+  // at once instead of waiting on one job's dependency chain at a time; a
+  // column depends only on columns of its job that start in earlier waves,
+  // so the order is topological.
   {
     int wmax = 0;
     for (int i = 0; i < nj; ++i) wmax = std::max(wmax, sz[i].p.nwaves);
@@ -288,9 +294,9 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   int grid = device_cu_count() * batch_occupancy(kc);
   if (grid < 1) grid = 1;
   ok = ok && launch_batch(kc, reinterpret_cast<const JobDev *>(d_ + off_jobs), nj,
-                          reinterpret_cast<const int64_t *>(d_ + off_jt),
+                          reinterpret_cast<const int64_t *>(d_ + off_jc),
                           reinterpret_cast<int32_t *>(d_ + off_qjob),
-                          reinterpret_cast<int32_t *>(d_ + off_qtile), tiles,
+                          reinterpret_cast<int32_t *>(d_ + off_qtile), tiles, jc[nj],
                           reinterpret_cast<int32_t *>(d_ + off_flags),
                           reinterpret_cast<Ctrl *>(d_ + off_ctrl), grid, stream_) == 0;
   ok = ok && hipMemcpyAsync(h_out_, d_ + off_out, (size_t)out_bytes, hipMemcpyDeviceToHost,

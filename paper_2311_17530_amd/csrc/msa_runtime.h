@@ -21,9 +21,9 @@ int fill_occupancy(int k);
 int launch_prune_bounds(const PruneDev &pd, Ctrl *ctrl, hipStream_t s);
 int launch_prune_select(const PruneDev &pd, Ctrl *ctrl, int pass, hipStream_t s);
 int launch_prune_check(const PruneDev &pd, Ctrl *ctrl, hipStream_t s);
-int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_jtiles,
-                 int32_t *qjob, int32_t *qtile, int64_t total, int32_t *flags, Ctrl *ctrl,
-                 int grid, hipStream_t s);
+int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_jcols,
+                 int32_t *qjob, int32_t *qtile, int64_t tiles, int64_t cols, int32_t *flags,
+                 Ctrl *ctrl, int grid, hipStream_t s);
 int batch_occupancy(int kclass);
 
 // runtime (msa_runtime.cpp)
