@@ -795,9 +795,11 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
 // become one-residue columns (sequence 0 first in the output).
 // coopt: the direction bytes are tie sets; the walk takes the lowest mask of
 // each, which is the decision of the plain mode.
-template <int K>
-__device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb, bool egf = false,
-                              int64_t best = 0, bool coopt = false) {
+// The modes are template parameters so that the plain walk's step loop has
+// no mode branches.
+template <int K, bool egf = false, bool coopt = false>
+__device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb,
+                              int64_t best = 0) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int M = C::M;
@@ -822,7 +824,7 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb, bo
     if ((Li & 63) == 0) jd.path[Li - 64 + tid] = (uint8_t)pbuf;
   };
   bool done = true;
-  if (egf) {
+  if constexpr (egf) {
     // end cell from its row-major index; the suffixes after it are emitted
     // first (the path is recorded end first): sequence k-1's, ..., sequence 0's
     int64_t lin = (int64_t)(uint32_t)best;
@@ -996,9 +998,14 @@ __global__ __launch_bounds__(64) void traceback_kernel(JobDev jd, Ctrl *ctrl) {
   __shared__ alignas(16) uint8_t dirb[Cfg<K>::DBS];
   const bool egf = (ctrl->flags & kEndGapsFree) != 0;
   const bool coopt = (ctrl->flags & kCoOptimal) != 0;
-  traceback_job<K>(jd, __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                   dirb, egf, __hip_atomic_load(&ctrl->best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                   coopt);
+  const int st = __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (egf)
+    traceback_job<K, true, false>(
+        jd, st, dirb, __hip_atomic_load(&ctrl->best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  else if (coopt)
+    traceback_job<K, false, true>(jd, st, dirb);
+  else
+    traceback_job<K, false, false>(jd, st, dirb);
   __syncthreads();
   if (threadIdx.x == 0) {
     // ready the control block for the next launch on this workspace
