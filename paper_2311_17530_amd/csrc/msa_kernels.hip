@@ -1432,7 +1432,8 @@ int launch_export(const JobDev &jd, const Ctrl *ctrl, uint8_t *out, int64_t ncel
 }  // namespace msa
 
 // ---------------------------------------------------------------------------
-// Batched launches: k class 0 covers k = 2..4, class 1 covers k = 5..8.
+// Batched launches: k class 0 covers k = 2..4, 1 is k = 5, 2 is k = 6, 3 covers
+// k = 7..8.
 // ---------------------------------------------------------------------------
 namespace msa {
 
@@ -1460,22 +1461,38 @@ static int launch_batch_k(const JobDev *d_jobs, int njobs, const int64_t *d_jcol
 int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_jcols,
                  int32_t *qjob, int32_t *qtile, int64_t tiles, int64_t cols, int32_t *flags,
                  Ctrl *ctrl, int grid, hipStream_t s) {
-  if (kclass == 0)
-    return launch_batch_k<2, 4>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
-                                grid, s);
-  return launch_batch_k<5, 8>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
-                              grid, s);
+  switch (kclass) {
+    case 0:
+      return launch_batch_k<2, 4>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
+                                  grid, s);
+    case 1:
+      return launch_batch_k<5, 5>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
+                                  grid, s);
+    case 2:
+      return launch_batch_k<6, 6>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
+                                  grid, s);
+    default:
+      return launch_batch_k<7, 8>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
+                                  grid, s);
+  }
+}
+
+template <int KLO, int KHI>
+static int batch_occupancy_k() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fill_kernel<KLO, KHI, kBatchThreads>,
+                                                   kBatchThreads, 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
 }
 
 int batch_occupancy(int kclass) {
-  int nb = 0;
-  hipError_t e = kclass == 0
-                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &nb, batch_fill_kernel<2, 4, kBatchThreads>, kBatchThreads, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &nb, batch_fill_kernel<5, 8, kBatchThreads>, kBatchThreads, 0);
-  if (e != hipSuccess) return 1;
-  return nb > 0 ? nb : 1;
+  switch (kclass) {
+    case 0: return batch_occupancy_k<2, 4>();
+    case 1: return batch_occupancy_k<5, 5>();
+    case 2: return batch_occupancy_k<6, 6>();
+    default: return batch_occupancy_k<7, 8>();
+  }
 }
 
 }  // namespace msa

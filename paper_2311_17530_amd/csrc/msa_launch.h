@@ -16,8 +16,11 @@ namespace msa {
 // Validation of one host job; returns MSA_OK or a status.
 int validate_job(const msa_job &j, int64_t aln_cap_needed_check = -1);
 
-// k class of the batched kernels: 0 for k = 2..4, 1 for k = 5..8.
-inline int kclass_of(int k) { return k <= 4 ? 0 : 1; }
+// k class of the batched kernels: 0 for k = 2..4, 1 for k = 5, 2 for k = 6,
+// 3 for k = 7..8.  A batched kernel takes the registers of its largest k, so
+// k = 5 and 6 get kernels of their own (k = 5 alone: 3 workgroups per CU
+// instead of 1 beside k = 8).
+inline int kclass_of(int k) { return k <= 4 ? 0 : k == 5 ? 1 : k == 6 ? 2 : 3; }
 
 // Device bytes one job needs inside a launch arena.
 int64_t job_arena_bytes(const msa_job &j);
