@@ -128,7 +128,7 @@ struct QItem {
 
 // Tile edge per k (LDS footprint (T+1)^k * 4 bytes for the score tile).
 constexpr int tile_edge_for_k(int k) {
-  return k == 2 ? 32 : k == 3 ? 16 : k == 4 ? 8 : k == 5 ? 5 : k == 6 ? 3 : 2;
+  return k == 2 ? 32 : k == 3 ? 16 : k == 4 ? 8 : k == 5 ? 4 : k == 6 ? 3 : 2;
 }
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }

@@ -35,12 +35,12 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // stride exceeds T times the sum of the strides after it, so every cell of the
 // (T+1)^k box has its own word.  Within that freedom they are chosen so that
 // one sweep step (consecutive lines on consecutive lanes) reads and writes
-// distinct LDS banks for k <= 4.
+// distinct LDS banks for k <= 5.
 template <int K> struct Strides;
 template <> struct Strides<2> { static constexpr int v[2] = {34, 1}; };
 template <> struct Strides<3> { static constexpr int v[3] = {305, 18, 1}; };
 template <> struct Strides<4> { static constexpr int v[4] = {801, 89, 10, 1}; };
-template <> struct Strides<5> { static constexpr int v[5] = {1296, 216, 36, 6, 1}; };
+template <> struct Strides<5> { static constexpr int v[5] = {709, 145, 26, 5, 1}; };
 template <> struct Strides<6> { static constexpr int v[6] = {1024, 256, 64, 16, 4, 1}; };
 template <> struct Strides<7> { static constexpr int v[7] = {733, 244, 81, 27, 9, 3, 1}; };
 template <> struct Strides<8> { static constexpr int v[8] = {2197, 733, 244, 81, 27, 9, 3, 1}; };
@@ -61,8 +61,8 @@ struct Cfg {
   // otherwise they are staged in LDS.
   static constexpr bool REGDIR = T % 4 == 0;
   // Neighbours one step back along the line are the values the lane read (or
-  // wrote) in the previous step: carried in registers for k <= 4.
-  static constexpr bool CARRY = K <= 4;
+  // wrote) in the previous step: carried in registers for k <= 5.
+  static constexpr bool CARRY = K <= 5;
   static constexpr int sstride(int i) { return Strides<K>::v[i]; }
   static constexpr int ns() {
     int s = 0;
@@ -433,11 +433,11 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     for (int cb = 0; cb <= K; ++cb) gk[cb] = (gap * cb * (K - cb)) * (1 << K);
 
     // Per lane and line: the word of cell (line, t = 0), the line's coordinate
-    // sum, and the pair-table rows of the pairs (i, k-1).  For k <= 4 the sums
+    // sum, and the pair-table rows of the pairs (i, k-1).  For k <= 5 the sums
     // of the pair scores within the line dimensions (fixed along the line) are
     // kept per neighbour mask b' over those dimensions; for larger k the pair
     // scores are read from LDS at every step.
-    constexpr bool LREG = K <= 4;
+    constexpr bool LREG = K <= 5;
     int idx0[U], sq[U], pto[U][KL], qv[U][KL];
     bool lv[U];
     int32_t lsum[LREG ? U : 1][LREG ? ML + 1 : 1];
