@@ -1023,9 +1023,15 @@ __global__ __launch_bounds__(64) void traceback_kernel(JobDev jd, Ctrl *ctrl) {
 // and every optimal alignment is one, so the alignments come in lexicographic
 // order of their column masks read from the last column to the first (the
 // first is the plain traceback's).  The stack of chosen masks lives in LDS
-// (sum n_i <= kCoMaxTotal); the direction block of the current cell's tile is
-// cached in LDS.  Alignment p goes to aln_out + p * k * aln_cap.
+// (sum n_i <= kCoMaxTotal), each entry with a flag (kMoreTies) when that cell
+// has tied masks above the one taken; after an alignment the walk jumps back
+// to the deepest flagged level with one wave-wide scan of the stack instead of
+// stepping back through the cells.  The direction block of the current cell's
+// tile is cached in LDS.  Alignment p goes to aln_out + p * k * aln_cap.
 // ---------------------------------------------------------------------------
+constexpr int kMoreTies = 0x80;  // stack entry flag: the cell has tied masks above it
+constexpr int kMaskBits = 0x7F;
+
 template <int K>
 __global__ __launch_bounds__(64) void coopt_kernel(JobDev jd, Ctrl *ctrl, int32_t max_paths,
                                                    uint8_t *aln_out, int64_t *len_out,
@@ -1044,7 +1050,7 @@ __global__ __launch_bounds__(64) void coopt_kernel(JobDev jd, Ctrl *ctrl, int32_
   int v[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) v[i] = jd.n[i];
-  int64_t cur_t = -1;  // tile whose block is in dirb
+  int cur_t = -1;  // tile whose block is in dirb
   int d = 0, np = 0;
   int tried = 0;       // masks up to this one were tried at depth d
   int64_t steps = 0;
@@ -1061,7 +1067,7 @@ __global__ __launch_bounds__(64) void coopt_kernel(JobDev jd, Ctrl *ctrl, int32_
       for (int i = 0; i < K; ++i) cnt[i] = 0;
       for (int c0 = 0; c0 < d; c0 += 64) {
         const int col = c0 + tid;
-        const int m = col < d ? path[d - 1 - col] : 0;
+        const int m = col < d ? (path[d - 1 - col] & kMaskBits) : 0;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
           const int bit = (m >> i) & 1;
@@ -1079,10 +1085,36 @@ __global__ __launch_bounds__(64) void coopt_kernel(JobDev jd, Ctrl *ctrl, int32_
       if (tid == 0) len_out[np] = d;
       ++np;
       if (np == max_paths || d == 0) break;
-      --d;  // back up one step and try the next tied mask there
-      tried = path[d];
+      // back up to the deepest level whose cell has untried tied masks: scan
+      // the stack 64 entries at a time (lane x reads level e - x), adding the
+      // masks of the levels popped to v
+      int e = d - 1, found = -1;
+      int back[K];
 #pragma unroll
-      for (int i = 0; i < K; ++i) v[i] += (tried >> i) & 1;
+      for (int i = 0; i < K; ++i) back[i] = 0;
+      while (e >= 0) {
+        const int lvl = e - tid;
+        const int ent = lvl >= 0 ? path[lvl] : 0;
+        const uint64_t flagged = __ballot((ent & kMoreTies) != 0);
+        // levels e, e-1, ... up to and including the first flagged one
+        const int upto = flagged ? __builtin_ctzll(flagged) : 63;
+        const bool popped = tid <= upto && lvl >= 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          const uint64_t bits = __ballot(popped && ((ent >> i) & 1));
+          back[i] += __builtin_popcountll(bits);
+        }
+        if (flagged) {
+          found = e - upto;
+          break;
+        }
+        e -= 64;
+      }
+      if (found < 0) break;  // every alignment has been produced
+#pragma unroll
+      for (int i = 0; i < K; ++i) v[i] += back[i];
+      d = found;
+      tried = path[d] & kMaskBits;
       continue;
     }
     if (++steps > step_limit) {  // corrupt tie data: never loop for ever
@@ -1090,17 +1122,17 @@ __global__ __launch_bounds__(64) void coopt_kernel(JobDev jd, Ctrl *ctrl, int32_
       break;
     }
     // tie set of cell v (its tile's block cached in LDS)
-    int64_t t = 0;
+    int t = 0;  // tile index (fewer than 2^30 tiles)
     int dl = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const int ci = v[i] == 0 ? 0 : (v[i] - 1) / T + 1;
-      t += (int64_t)ci * jd.tstride[i];
+      t += ci * jd.tstride[i];
       dl += (v[i] - (ci == 0 ? 0 : (ci - 1) * T + 1)) * C::dstride(i);
     }
     if (t != cur_t) {
       __syncthreads();
-      const uint4 *src = reinterpret_cast<const uint4 *>(jd.dir + t * C::DBS);
+      const uint4 *src = reinterpret_cast<const uint4 *>(jd.dir + (int64_t)t * C::DBS);
       uint4 *dst = reinterpret_cast<uint4 *>(dirb);
       for (int idx = tid; idx < NQ; idx += 64) dst[idx] = src[idx];
       __syncthreads();
@@ -1118,8 +1150,10 @@ __global__ __launch_bounds__(64) void coopt_kernel(JobDev jd, Ctrl *ctrl, int32_
         status = ST_EDEVICE;
         break;
       }
-      if (tid == 0) path[d] = (uint8_t)b;
-      __syncthreads();
+      // every lane stores the same byte; the one wave's LDS accesses stay in
+      // program order, so no barrier is needed before path[d] is read back
+      const bool more = (rest & ~((1 << b) - 1)) != 0;  // tied masks above b
+      path[d] = (uint8_t)(b | (more ? kMoreTies : 0));
 #pragma unroll
       for (int i = 0; i < K; ++i) v[i] -= (b >> i) & 1;
       ++d;
@@ -1132,7 +1166,7 @@ __global__ __launch_bounds__(64) void coopt_kernel(JobDev jd, Ctrl *ctrl, int32_
     }
     if (d == 0) break;  // every alignment has been produced
     --d;
-    tried = path[d];
+    tried = path[d] & kMaskBits;
 #pragma unroll
     for (int i = 0; i < K; ++i) v[i] += (tried >> i) & 1;
   }
