@@ -172,6 +172,8 @@ def bench_served(n_jobs=20000, loads=(0.7, 0.9), max_inflight=4, max_jobs=256):
             srv.wait(t)
         sat = n_jobs / (time.perf_counter() - t0)
         streams = [_served_stream(srv, jobs, load, sat) for load in loads]
+    if not streams:
+        return {"jobs": n_jobs, "saturated_jobs_per_s": round(sat, 2)}
     first = streams[0]
     return {"jobs": n_jobs, "ok": first["ok"],
             "saturated_jobs_per_s": round(sat, 2), "saturated_gcups": round(cells / (n_jobs / sat) / 1e9, 3),
