@@ -108,12 +108,22 @@ _SIGS = {
 
 
 def lib():
-    """Load the library (raises FileNotFoundError when it was not built)."""
+    """Load the library (raises FileNotFoundError when it was not built).
+
+    PyTorch (when installed) is imported first: its wheel ships its own HIP
+    runtime under the same soname, and the library must bind to that copy.
+    Loaded the other way round, the process would hold two HIP runtimes,
+    torch could not initialise its device afterwards, and device pointers and
+    streams would not be shared between the two."""
     global _lib
     if _lib is None:
         if not LIB_PATH.exists():
             raise FileNotFoundError(
                 f"{LIB_PATH} is missing: build it with `python -m paper_2311_17530_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         h = ctypes.CDLL(str(LIB_PATH))
         for name, (res, args) in _SIGS.items():
             fn = getattr(h, name)
