@@ -85,6 +85,20 @@ def test_tile_boundary_lengths(k):
         check_device(seqs, sub, gap)
 
 
+def test_three_sequence_column_shapes():
+    # Three sequences run as columns along dimension 0, swept in one pass with
+    # a ring of layers: long first sequences wrap the ring many times, short
+    # ones end inside a tile, and ragged or empty cross-sections change the
+    # skew of each column.
+    rng = np.random.Generator(np.random.PCG64(2500))
+    for lens in ([150, 20, 19], [151, 33, 1], [7, 40, 35], [16, 16, 48], [0, 30, 45],
+                 [97, 0, 17], [1, 1, 1], [200, 5, 3], [33, 17, 0]):
+        protein = bool(sum(lens) % 2)
+        sub, gap = protein_scoring() if protein else dna_scoring()
+        seqs = [rng.integers(0, sub.shape[0], size=n).astype(np.uint8) for n in lens]
+        check_device(seqs, sub, gap)
+
+
 def test_empty_and_degenerate():
     sub, gap = dna_scoring()
     e = np.zeros(0, np.uint8)
