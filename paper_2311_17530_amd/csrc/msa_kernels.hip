@@ -33,13 +33,14 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // LDS word strides of the tile with halo, dimension k-1 last (stride 1).  Each
 // stride exceeds T times the sum of the strides after it, so every cell of the
-// (T+1)^k box has its own word.  Within that freedom they are chosen so that
-// one sweep step (consecutive lines on consecutive lanes) reads and writes
-// distinct LDS banks for k <= 5.
+// (T+1)^k box has its own word.  Within that freedom they are chosen to spread
+// one sweep step's accesses over the LDS banks for the lanes' lines
+// (LineOrder): consecutive lines for k <= 3, coordinate-sum order for k = 4;
+// k = 5 keeps the strides chosen for consecutive lines.
 template <int K> struct Strides;
 template <> struct Strides<2> { static constexpr int v[2] = {34, 1}; };
 template <> struct Strides<3> { static constexpr int v[3] = {305, 18, 1}; };
-template <> struct Strides<4> { static constexpr int v[4] = {801, 89, 10, 1}; };
+template <> struct Strides<4> { static constexpr int v[4] = {743, 82, 9, 1}; };
 template <> struct Strides<5> { static constexpr int v[5] = {709, 145, 26, 5, 1}; };
 template <> struct Strides<6> { static constexpr int v[6] = {1024, 256, 64, 16, 4, 1}; };
 template <> struct Strides<7> { static constexpr int v[7] = {733, 244, 81, 27, 9, 3, 1}; };
@@ -92,12 +93,45 @@ struct Cfg {
   }
 };
 
+// Lane p of the sweep takes line v[p].  For k >= 4 the lines are in
+// ascending order of their coordinate sum (ties by line index): a line with
+// sum s is active in steps s .. s + T - 1, so a wave whose lines have nearly
+// equal sums issues the step body in few more steps than one line needs,
+// where consecutive line indices span a sum range of about 2T (129^4 fill
+// 2.27 -> 1.89 ms).  For k <= 3 the fill is bound by the latency of its steps
+// rather than by issue, and consecutive lines keep the LDS banks apart, so
+// the order is the identity.
+template <int K>
+struct LineOrder {
+  uint16_t v[Cfg<K>::L];
+  constexpr LineOrder() : v() {
+    constexpr int T = Cfg<K>::T, L = Cfg<K>::L, KL = K - 1;
+    int p = 0;
+    if (K <= 3) {
+      for (int l = 0; l < L; ++l) v[l] = (uint16_t)l;
+      return;
+    }
+    for (int s = 0; s <= KL * (T - 1); ++s)
+      for (int l = 0; l < L; ++l) {
+        int rem = l, sum = 0;
+        for (int i = 0; i < KL; ++i) {
+          sum += rem % T;
+          rem /= T;
+        }
+        if (sum == s) v[p++] = (uint16_t)l;
+      }
+  }
+};
+template <int K>
+__device__ const LineOrder<K> kLineOrder{};
+
 template <int K>
 struct Smem {
   int32_t S[Cfg<K>::NS];                                // tile keys with halo
   int32_t PT[Cfg<K>::NP * Cfg<K>::T * Cfg<K>::T];       // pair scores << k
   int32_t SUB[kSubLds * kSubLds];                       // substitution matrix << k
   uint8_t RES[K * Cfg<K>::T];                           // residues of the tile
+  uint16_t LORD[K <= 3 ? 1 : Cfg<K>::L];                // LineOrder<K> (k >= 4)
   alignas(16) uint8_t DIRB[Cfg<K>::REGDIR ? 16 : Cfg<K>::DBS];  // staged direction bytes
 };
 
@@ -150,6 +184,8 @@ __device__ void load_tables(const JobDev &jd, int alpha, Smem<K> &sm) {
   if (alpha <= kSubLds)
     for (int e = tid; e < alpha * alpha; e += NT)
       sm.SUB[(e / alpha) * kSubLds + e % alpha] = ((int32_t)jd.sub[e]) * (1 << K);
+  if constexpr (K >= 4)
+    for (int p = tid; p < Cfg<K>::L; p += NT) sm.LORD[p] = kLineOrder<K>.v[p];
 }
 
 // Appends one byte at the top of a little-endian register queue of NR words
@@ -417,7 +453,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
 #pragma unroll
     for (int i = 0; i < K; ++i) s += C::sstride(i);
     sm.S[s] = 0;
-    if constexpr (C::REGDIR)
+    if constexpr (C::REGDIR)  // lane 0 holds line 0 (coordinate sum 0)
       dr[0][0] = tid == 0 ? (coopt ? 0u : (uint32_t)M) : 0u;  // mask 0 / empty tie set
     else
       sm.DIRB[0] = (uint8_t)(coopt ? 0 : M);
@@ -439,11 +475,15 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     // scores are read from LDS at every step.
     constexpr bool LREG = K <= 5;
     int idx0[U], sq[U], pto[U][KL], qv[U][KL];
+    int ln[C::REGDIR ? 1 : U];  // the lanes' lines (staged direction bytes)
     bool lv[U];
     int32_t lsum[LREG ? U : 1][LREG ? ML + 1 : 1];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int l = tid + u * NT;
+      const int pl = tid + u * NT;
+      // the lane's line (k >= 4: coordinate-sum order; k <= 3: the identity)
+      const int l = K <= 3 ? pl : pl < L ? (int)sm.LORD[pl] : L;
+      if constexpr (!C::REGDIR) ln[u] = l;
       int rem = l;
 #pragma unroll
       for (int i = KL - 1; i >= 0; --i) {
@@ -566,7 +606,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
         if constexpr (C::REGDIR)
           shift_in<NR>(dr[u], byte);
         else
-          sm.DIRB[(tid + u * NT) * T + t] = (uint8_t)byte;
+          sm.DIRB[ln[u] * T + t] = (uint8_t)byte;
       }
       __syncthreads();
     }
@@ -706,8 +746,9 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     if constexpr (C::REGDIR) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int l = tid + u * NT;
-        if (l < L) {
+        const int pl = tid + u * NT;
+        if (pl < L) {
+          const int l = K <= 3 ? pl : (int)sm.LORD[pl];  // the line this lane swept
           if constexpr (NR % 4 == 0) {
             uint4 *dst = reinterpret_cast<uint4 *>(blk + l * T);
 #pragma unroll
