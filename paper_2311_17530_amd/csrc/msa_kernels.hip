@@ -197,6 +197,39 @@ __device__ inline void shift_in(uint32_t (&d)[NR], uint32_t byte) {
   d[NR - 1] = (d[NR - 1] >> 8) | (byte << 24);
 }
 
+// The halo slots a lane fills: slot tid + it * NT of the (T+1)^(k-1) cells of
+// one face layer, as its base-(T+1) digits (least significant first, HB bits
+// each), with bit 31 set for slots beyond the layer.  They do not depend on
+// the tile, so for up to four slots per lane (k <= 7) they are computed once
+// per workgroup instead of by division in every tile; k = 8 (nine slots,
+// every register taken) computes them per tile.
+template <int K, int NT>
+struct HaloSlots {
+  static constexpr int E = Cfg<K>::E;
+  static constexpr int CNT = ipow(E, K - 1);
+  static constexpr int IT = (CNT + NT - 1) / NT;
+  static constexpr int HB = bits_for(E - 1);
+  static constexpr bool PRE = IT <= 4;
+  static_assert((K - 1) * HB <= 31, "digits fit below bit 31");
+  uint32_t d[PRE ? IT : 1];
+  __device__ static uint32_t compute(int tid, int it) {
+    const int idx = tid + it * NT;
+    uint32_t w = idx < CNT ? 0u : 0x80000000u;
+    int rem = idx;
+#pragma unroll
+    for (int q = 0; q < K - 1; ++q) {
+      w |= (uint32_t)(rem % E) << (q * HB);
+      rem /= E;
+    }
+    return w;
+  }
+  __device__ explicit HaloSlots(int tid) {
+#pragma unroll
+    for (int it = 0; it < (PRE ? IT : 1); ++it) d[it] = PRE ? compute(tid, it) : 0u;
+  }
+  __device__ static int digit(uint32_t w, int q) { return (int)((w >> (q * HB)) & ((1u << HB) - 1)); }
+};
+
 // ---------------------------------------------------------------------------
 // One tile of the fill.
 // ---------------------------------------------------------------------------
@@ -216,7 +249,8 @@ __device__ inline void shift_in(uint32_t (&d)[NR], uint32_t byte) {
 // exported.
 template <int K, int NT, int SYNC>
 __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int epoch,
-                             Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm, bool egf = false,
+                             Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm,
+                             const HaloSlots<K, NT> &hs, bool egf = false,
                              int64_t *best_key = nullptr, bool coopt = false,
                              bool prune = false, bool own0 = false, bool cols = false) {
   using C = Cfg<K>;
@@ -363,18 +397,34 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
   // ---- halo: layer l_i = 0 along each dimension ----
   // Loads first, LDS stores after: for small k every face load of every
   // dimension is in flight at once (one memory round trip per tile).
+  // The slot digits are made opaque here, like the thread index, so that
+  // nothing derived from them is kept live across the persistent loop.
+  using HS = HaloSlots<K, NT>;
+  uint32_t hd[HS::PRE ? HS::IT : 1];
+  if constexpr (HS::PRE) {
+#pragma unroll
+    for (int it = 0; it < HS::IT; ++it) {
+      hd[it] = hs.d[it];
+      asm volatile("" : "+v"(hd[it]));
+    }
+  }
+  // slot word it: precomputed, or (k = 8) computed where it is used
+  auto slot = [&](int it) -> uint32_t {
+    if constexpr (HS::PRE)
+      return hd[it];
+    else
+      return HS::compute(tid, it);
+  };
   if (own0) {
     // layer l_0 = 0 is the previous tile's last layer (l_0 = its extent)
     const int e0 = c[0] - 1 == 0 ? 1 : T;
-    constexpr int cnt = ipow(E, K - 1);
-    for (int idx = tid; idx < cnt; idx += NT) {
-      int rem = idx, s = 0;
 #pragma unroll
-      for (int j = K - 1; j >= 1; --j) {
-        s += (rem % E) * C::sstride(j);
-        rem /= E;
-      }
-      sm.S[s] = sm.S[s + e0 * C::sstride(0)];
+    for (int it = 0; it < HS::IT; ++it) {
+      const uint32_t w = slot(it);
+      int s = 0;
+#pragma unroll
+      for (int j = K - 1; j >= 1; --j) s += HS::digit(w, K - 1 - j) * C::sstride(j);
+      if ((w >> 31) == 0) sm.S[s] = sm.S[s + e0 * C::sstride(0)];
     }
   }
   {
@@ -395,17 +445,15 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
                        : jd.faces;
 #pragma unroll
           for (int it = 0; it < CH; ++it) {
-            const int idx = tid + (it0 + it) * NT;
-            int rem = idx;
-            int s = 0;
-            bool valid = idx < cnt, neg = (c[i] == 0);
+            const uint32_t w = slot(it0 + it);
+            int s = 0, q = 0;
+            bool valid = (w >> 31) == 0, neg = (c[i] == 0);
             int64_t foff = 0;
             int src = 1 << i;  // the cell lies in tile c - e_src
 #pragma unroll
             for (int j = K - 1; j >= 0; --j) {
               if (j == i) continue;
-              const int l = rem % E;
-              rem /= E;
+              const int l = HS::digit(w, q++);
               valid = valid && l <= ext[j];
               s += l * C::sstride(j);
               const int v = lo[j] - 1 + l;
@@ -796,6 +844,7 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
   const int nq = prune ? __builtin_amdgcn_readfirstlane(ctrl->nqueue)
                        : cols ? jd.ncols : jd.ntiles;
   load_tables<K, NT>(jd, alpha, sm);
+  const HaloSlots<K, NT> hs(threadIdx.x);
   const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   static_assert(NT % 64 == 0, "whole waves per workgroup");
@@ -817,11 +866,11 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
       const int base = __builtin_amdgcn_readfirstlane(jd.corder[qi]);
       for (int c0 = 0; c0 < jd.P[0]; ++c0)
         process_tile<K, NT, SYNC>(jd, alpha, gap, base + c0 * jd.tstride[0], epoch, ctrl,
-                                  &ctrl->status, sm, egf, &ctrl->best, coopt, false, c0 > 0,
-                                  true);
+                                  &ctrl->status, sm, hs, egf, &ctrl->best, coopt, false,
+                                  c0 > 0, true);
     } else {
       process_tile<K, NT, SYNC>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]),
-                                epoch, ctrl, &ctrl->status, sm, egf, &ctrl->best, coopt,
+                                epoch, ctrl, &ctrl->status, sm, hs, egf, &ctrl->best, coopt,
                                 prune);
     }
   }
@@ -1337,9 +1386,10 @@ __device__ void batch_column(const JobDev &jd, int base, int epoch, Ctrl *ctrl, 
     cur_k = K;
     cur_sub = jd.sub;
   }
+  const HaloSlots<K, NT> hs(threadIdx.x);
   for (int c0 = 0; c0 < jd.P[0]; ++c0)
     process_tile<K, NT, 2>(jd, jd.alpha, jd.gap, base + c0 * jd.tstride[0], epoch, ctrl,
-                           jd.jstatus, sm, false, nullptr, false, false, c0 > 0, true);
+                           jd.jstatus, sm, hs, false, nullptr, false, false, c0 > 0, true);
 }
 
 template <int KLO, int KHI, int NT>
