@@ -41,7 +41,10 @@ sys.path.insert(0, ROOT)
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.3 T int32 lane-ops/s
 PEAK_HBM_GBS = 8000.0
 MAIN = "prot_k3_512"
-EXTRA = ["prot_k4_128", "dna_k3_40"]
+EXTRA = ["prot_k4_128", "prot_k5_40", "dna_k3_40"]
+# Served stream: fixed Poisson arrival rates (jobs/s), the same on every run
+# so that p50/p99 compare across runs and machines.
+SERVED_RATES = (4000.0, 7000.0)
 
 
 def time_workload(name, steps, warmup, end_gaps_free=False, prune=False):
@@ -154,75 +157,136 @@ def bench_batched(n_jobs=4096, n_plain=256):
             "speedup_vs_sequential": round((n_jobs / dt) / (n_plain / dtp), 2)}
 
 
-def bench_served(n_jobs=20000, loads=(0.7, 0.9), max_inflight=4, max_jobs=256):
-    """Served path: saturated throughput X (all jobs submitted at once), then
-    Poisson streams at load * X for each load, with per-job latency from
-    arrival to result."""
+def bench_served(n_jobs=20000, rates=SERVED_RATES, max_inflight=4, max_jobs=256,
+                 n_plain=1000):
+    """Served path on the 20000-job mix.
+
+    Jobs are marshalled into C job structs before any timing, so the timed
+    windows hold only the library's submit calls and the device work.
+    - saturated: every job submitted at t=0 by one thread while another
+      thread waits for the results in order; jobs/s over the wall time, and
+      the server's own device-busy time (union of its launches' device
+      intervals, HIP events) beside it, with the host's share (submit calls)
+      timed separately;
+    - streams: Poisson arrivals at each fixed rate in `rates` (jobs/s), per
+      job latency from its arrival to its result (p50/p99);
+    - sequential: the first `n_plain` jobs of the mix one at a time through
+      the plain path (one msa_dp_align call each)."""
     import paper_2311_17530_amd as msa
     from msa_inputs import served_jobs
 
     jobs = served_jobs(n_jobs)
     cells = sum(j.cells for j in jobs)
+    pre = _Marshalled(jobs)
+    out = {"jobs": n_jobs, "cells": cells,
+           "max_inflight_launches": max_inflight, "max_jobs_per_launch": max_jobs}
     with msa.Server(max_inflight=max_inflight, max_jobs_per_launch=max_jobs) as srv:
-        for j in jobs[:32]:  # warm-up
-            srv.wait(srv.submit(j.seqs, j.sub, j.gap))
+        for i in range(32):  # warm-up: arenas, code load
+            srv.wait(srv.submit(jobs[i].seqs, jobs[i].sub, jobs[i].gap))
+        st0 = srv.stats()
+        wall, submit_s, ok = pre.run_saturated(srv)
+        st1 = srv.stats()
+        busy = (st1["busy_us"] - st0["busy_us"]) / 1e6
+        out.update({"ok": ok, "saturated_jobs_per_s": round(n_jobs / wall, 2),
+                    "saturated_gcups": round(cells / wall / 1e9, 3),
+                    "saturated_seconds": round(wall, 4),
+                    "submit_seconds": round(submit_s, 4),
+                    "device_busy_seconds": round(busy, 4),
+                    "device_busy_fraction": round(busy / wall, 3),
+                    "device_jobs_per_s": round(n_jobs / busy, 2) if busy > 0 else None,
+                    "launches": st1["launches"] - st0["launches"]})
+        streams = [pre.run_stream(srv, rate) for rate in rates]
+    out["streams"] = streams
+    if streams:
+        out.update({"arrival_rate_per_s": streams[0]["arrival_rate_per_s"],
+                    "jobs_per_s": streams[0]["jobs_per_s"],
+                    "latency_ms_p50": streams[0]["latency_ms_p50"],
+                    "latency_ms_p99": streams[0]["latency_ms_p99"]})
+    if n_plain:
+        msa.align(jobs[0].seqs, jobs[0].sub, jobs[0].gap)
         t0 = time.perf_counter()
-        tickets = [srv.submit(j.seqs, j.sub, j.gap) for j in jobs]
-        for t in tickets:
-            srv.wait(t)
-        sat = n_jobs / (time.perf_counter() - t0)
-        streams = [_served_stream(srv, jobs, load, sat) for load in loads]
-    if not streams:
-        return {"jobs": n_jobs, "saturated_jobs_per_s": round(sat, 2)}
-    first = streams[0]
-    return {"jobs": n_jobs, "ok": first["ok"],
-            "saturated_jobs_per_s": round(sat, 2), "saturated_gcups": round(cells / (n_jobs / sat) / 1e9, 3),
-            "arrival_rate_per_s": first["arrival_rate_per_s"], "load": first["load"],
-            "jobs_per_s": first["jobs_per_s"],
-            "latency_ms_p50": first["latency_ms_p50"], "latency_ms_p99": first["latency_ms_p99"],
-            "streams": streams,
-            "max_inflight_launches": max_inflight, "max_jobs_per_launch": max_jobs}
+        for j in jobs[:n_plain]:
+            msa.align(j.seqs, j.sub, j.gap)
+        dt = time.perf_counter() - t0
+        out["sequential_plain_jobs_per_s"] = round(n_plain / dt, 2)
+        out["sequential_plain_sample"] = f"first {n_plain} jobs, one msa_dp_align call each"
+        out["speedup_vs_sequential"] = round(out["saturated_jobs_per_s"] / (n_plain / dt), 2)
+    return out
 
 
-def _served_stream(srv, jobs, load, sat):
-    """One Poisson stream of `jobs` at load * sat jobs/s through `srv`."""
-    import threading
+class _Marshalled:
+    """Jobs of a stream as C job structs and result buffers, built once."""
 
-    from msa_inputs import poisson_arrivals
+    def __init__(self, jobs):
+        import ctypes
 
-    n_jobs = len(jobs)
-    rate = load * sat
-    arr = poisson_arrivals(n_jobs, rate)
-    tick = [None] * n_jobs
-    t_sub = np.zeros(n_jobs)
-    t_done = np.zeros(n_jobs)
-    status = np.zeros(n_jobs, dtype=np.int64)
-    ready = threading.Semaphore(0)
+        import paper_2311_17530_amd as msa
+        from paper_2311_17530_amd._lib import MsaResult, _make_job
+        self.ctypes = ctypes
+        self.msa = msa
+        self.keep = []
+        self.n = len(jobs)
+        self.cj = [_make_job(j.seqs, j.sub, j.gap, self.keep) for j in jobs]
+        caps = [max(1, sum(j.lens)) for j in jobs]
+        self.bufs = [np.empty((j.k, c), np.uint8) for j, c in zip(jobs, caps)]
+        self.res = [MsaResult() for _ in jobs]
+        for r, b, c in zip(self.res, self.bufs, caps):
+            r.aln = b.ctypes.data
+            r.aln_cap = c
 
-    def waiter():
-        for i in range(n_jobs):
+    def _waiter(self, srv, tick, ready, t_done, status):
+        lib = self.msa.lib()
+        for i in range(self.n):
             ready.acquire()
-            r = srv.wait(tick[i])
+            rc = lib.msa_server_wait(srv.h, tick[i], self.ctypes.byref(self.res[i]), -1)
             t_done[i] = time.perf_counter()
-            status[i] = r[0]
+            status[i] = rc
 
-    th = threading.Thread(target=waiter)
-    th.start()
-    start = time.perf_counter()
-    for i, j in enumerate(jobs):
-        now = time.perf_counter() - start
-        if arr[i] > now:
-            time.sleep(arr[i] - now)
-        t_sub[i] = time.perf_counter()
-        tick[i] = srv.submit(j.seqs, j.sub, j.gap)
-        ready.release()
-    th.join()
-    span = t_done.max() - start
-    lat = (t_done - t_sub) * 1e3
-    return {"load": load, "arrival_rate_per_s": round(rate, 2), "ok": int((status == 0).sum()),
-            "jobs_per_s": round(n_jobs / span, 2),
-            "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
-            "latency_ms_p99": round(float(np.percentile(lat, 99)), 3)}
+    def _go(self, srv, arrivals):
+        import threading
+        lib = self.msa.lib()
+        ct = self.ctypes
+        n = self.n
+        tick = [0] * n
+        t_sub = np.zeros(n)
+        t_done = np.zeros(n)
+        status = np.zeros(n, dtype=np.int64)
+        ready = threading.Semaphore(0)
+        th = threading.Thread(target=self._waiter, args=(srv, tick, ready, t_done, status))
+        th.start()
+        t = ct.c_uint64()
+        submit_s = 0.0
+        start = time.perf_counter()
+        for i in range(n):
+            if arrivals is not None:
+                now = time.perf_counter() - start
+                if arrivals[i] > now:
+                    time.sleep(arrivals[i] - now)
+            t0 = time.perf_counter()
+            rc = lib.msa_server_submit(srv.h, ct.byref(self.cj[i]), ct.byref(t))
+            submit_s += time.perf_counter() - t0
+            if rc != 0:
+                raise self.msa.MsaError(rc, "msa_server_submit")
+            t_sub[i] = t0 if arrivals is None else start + arrivals[i]
+            tick[i] = t.value
+            ready.release()
+        th.join()
+        return start, t_sub, t_done, status, submit_s
+
+    def run_saturated(self, srv):
+        start, _, t_done, status, submit_s = self._go(srv, None)
+        return float(t_done.max() - start), submit_s, int((status == 0).sum())
+
+    def run_stream(self, srv, rate):
+        from msa_inputs import poisson_arrivals
+        arr = poisson_arrivals(self.n, rate)
+        start, t_sub, t_done, status, _ = self._go(srv, arr)
+        span = t_done.max() - start
+        lat = (t_done - t_sub) * 1e3
+        return {"arrival_rate_per_s": rate, "ok": int((status == 0).sum()),
+                "jobs_per_s": round(self.n / span, 2),
+                "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                "latency_ms_p99": round(float(np.percentile(lat, 99)), 3)}
 
 
 def measured_traffic():
@@ -245,18 +309,90 @@ def measured_traffic():
     return int(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline():
+def host_cpu():
+    """Model name, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(reps=3):
+    """The oracle (plain single-threaded C) on the full k=3 / 512 alignment,
+    median of `reps` runs with the calling thread pinned to one CPU."""
     from msa_inputs import workload
     from oracle import build_oracle_lib, oracle_align
 
     build_oracle_lib(force=False)
     job = workload(MAIN)
-    t0 = time.perf_counter()
-    oracle_align(job.seqs, job.sub, job.gap)
-    dt = time.perf_counter() - t0
+    old = os.sched_getaffinity(0)
+    cpu = min(old)
+    os.sched_setaffinity(0, {cpu})
+    try:
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle_align(job.seqs, job.sub, job.gap)
+            times.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, old)
+    dt = float(np.median(times))
     return {"value": job.cells / dt / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
-            "sample": f"one full {MAIN} alignment (fill + traceback, "
-                      f"{job.cells} cells) in {dt:.2f} s, single thread, gcc -O2"}
+            "sample": f"{reps} full {MAIN} alignments (fill + traceback, {job.cells} cells "
+                      f"each), median {dt:.2f} s, one thread pinned to CPU {cpu}, gcc -O2",
+            "seconds": [round(t, 3) for t in times]}
+
+
+def sclk_during(fn, seconds=0.4):
+    """GPU shader clock (MHz) read with rocm-smi while `fn` runs back to back
+    on the device; None when rocm-smi is not usable here."""
+    import subprocess
+    import threading
+
+    import torch
+    stop = threading.Event()
+
+    def spin():
+        while not stop.is_set():
+            fn()
+            torch.cuda.synchronize()
+
+    th = threading.Thread(target=spin)
+    th.start()
+    try:
+        time.sleep(seconds)
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
+                           text=True, timeout=20)
+        data = json.loads(r.stdout) if r.returncode == 0 else {}
+    except Exception:  # noqa: BLE001 -- the clock is context only
+        data = {}
+    finally:
+        stop.set()
+        th.join()
+    for card in data.values():
+        if isinstance(card, dict):
+            for key, val in card.items():
+                if ("sclk" in key.lower() and isinstance(val, str)
+                        and "mhz" in val.lower()):
+                    digits = "".join(c for c in val if c.isdigit())
+                    if digits:
+                        return int(digits)
+    return None
+
+
+def _sclk_main():
+    import paper_2311_17530_amd as msa
+    from msa_inputs import workload
+    job = workload(MAIN)
+    dev = msa.DeviceAligner(job.lens, job.sub, job.gap)
+    dev.set_sequences(job.seqs)
+    return sclk_during(dev.run_fill)
 
 
 def copy_probe(nbytes, steps):
@@ -311,6 +447,8 @@ def main():
         for name in [MAIN] + EXTRA:
             extra[name + "_pruned"] = time_workload(name, a.steps, a.warmup, prune=True)
     achieved = main_r["fill_tops"]
+    traffic = measured_traffic()
+    fill_s = main_r["fill_ms_avg"] / 1e3
     line = {
         "metric": "GCUPS",
         "value": round(main_r["gcups"], 3),
@@ -332,12 +470,20 @@ def main():
         "traceback_ms": round(main_r["traceback_ms_avg"], 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_INT32_TOPS, 2), "unit": "Tops/s",
-                     "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": measured_traffic(),
+                     "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": traffic,
+                     "hbm_gbs": round(traffic / fill_s / 1e9, 1) if traffic else None,
+                     "hbm_frac": round(traffic / fill_s / 1e9 / PEAK_HBM_GBS, 4)
+                     if traffic else None,
+                     "algorithmic_bytes": main_r["cells"],
+                     "algorithmic_hbm_frac": round(main_r["cells"] / fill_s / 1e9 / PEAK_HBM_GBS,
+                                                   4),
                      "kernel": "fill_kernel<3,256,2> (k=3, T=16, one line per lane)",
                      "ops_per_launch": 2 * main_r["neighbour_updates"]},
         "extra": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                       for kk, vv in v.items()} for k, v in extra.items()},
     }
+    line["host"] = host_cpu()
+    line["sclk_mhz_during_fill"] = _sclk_main()
     if not a.no_batched:
         line["batched"] = bench_batched()
     if not a.no_served:

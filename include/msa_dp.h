@@ -295,6 +295,15 @@ int msa_server_wait(msa_server *srv, uint64_t ticket, msa_result *out,
                     int64_t timeout_us);
 void msa_server_destroy(msa_server *srv);
 
+/* msa_server_stats: counters of the server so far, for measurement.  Writes
+ * the first n of: [0] launches completed, [1] jobs completed, [2] device
+ * busy time in microseconds (the union of the completed launches' device
+ * intervals, each from its input copy to its output copy, measured with HIP
+ * events), [3] span in microseconds from the first launch's start to the
+ * last launch's end, [4] jobs queued and not yet admitted.  Returns MSA_OK
+ * or MSA_EINVAL. */
+int msa_server_stats(msa_server *srv, int64_t *out, int32_t n);
+
 /* ------------------------------------------------------------------------
  * Host-side helpers (no device needed), exposed for tests and tools.
  * ---------------------------------------------------------------------- */
@@ -305,6 +314,16 @@ void msa_server_destroy(msa_server *srv);
  * +-sum(n_i)*C(k,2)*max(|gap|, max|sub|).  Returns MSA_OK or MSA_EINVAL. */
 int msa_dp_score_bounds(const int32_t *lens, int32_t k, const int8_t *submat,
                         int32_t alpha, int32_t gap, int64_t *lo, int64_t *hi);
+
+/* Validation of a shape, scoring and mode flags without a device: the
+ * checks msa_dp_prepare_ex makes before touching the workspace (k, lengths,
+ * flags, symmetric matrix, and the closed-form range check of every key the
+ * fill can form in that mode; for MSA_PRUNE that includes the -infinity keys
+ * that travel through kept tiles whose lower neighbours were pruned, along a
+ * monotone path of up to sum(n_i) cells).  Returns MSA_OK, MSA_EINVAL or
+ * MSA_ERANGE. */
+int msa_dp_check_scoring(const int32_t *lens, int32_t k, const int8_t *submat,
+                         int32_t alpha, int32_t gap, uint32_t flags);
 
 /* Tile edge (interior cells per dimension) the library uses for k. */
 int32_t msa_dp_tile_edge(int32_t k);

@@ -11,6 +11,7 @@ Workloads (the paper gives no datasets; these stand in for them):
   dna_k3_40      k=3 DNA, length 40 each, +2/-1, gap -2            (seed 1)
   prot_k3_512    k=3 protein, length 512 each, gap -8              (seed 2)
   prot_k4_128    k=4 protein, length 128 each, gap -8              (seed 3)
+  prot_k5_40     k=5 protein, length 40 each, gap -8               (seed 7)
   batch_4096     4096 jobs, k in {3,4}, lengths 16..160, DNA/protein (seed 4)
   served_20000   20000 jobs, k in {3,4,5}, Poisson arrivals       (seeds 5, 6)
 """

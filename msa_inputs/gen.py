@@ -135,6 +135,7 @@ WORKLOADS = {
     "dna_k3_40": dict(k=3, n=40, seed=1, protein=False),
     "prot_k3_512": dict(k=3, n=512, seed=2, protein=True),
     "prot_k4_128": dict(k=4, n=128, seed=3, protein=True),
+    "prot_k5_40": dict(k=5, n=40, seed=7, protein=True),
 }
 
 

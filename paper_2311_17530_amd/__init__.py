@@ -25,6 +25,7 @@ from ._lib import (  # noqa: F401
     align_coopt,
     exported_names,
     lib,
+    check_scoring,
     score_bounds,
     strerror,
     tile_edge,

@@ -99,8 +99,11 @@ _SIGS = {
     "msa_server_wait": (ctypes.c_int, [c_vp, ctypes.c_uint64, ctypes.POINTER(MsaResult),
                                        ctypes.c_int64]),
     "msa_server_destroy": (None, [c_vp]),
+    "msa_server_stats": (ctypes.c_int, [c_vp, c_i64p, ctypes.c_int32]),
     "msa_dp_score_bounds": (ctypes.c_int, [c_i32p, ctypes.c_int32, c_vp, ctypes.c_int32,
                                            ctypes.c_int32, c_i64p, c_i64p]),
+    "msa_dp_check_scoring": (ctypes.c_int, [c_i32p, ctypes.c_int32, c_vp, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_uint32]),
     "msa_dp_tile_edge": (ctypes.c_int32, [ctypes.c_int32]),
     "msa_dp_tile_grid": (ctypes.c_int32, [c_i32p, ctypes.c_int32, ctypes.c_int32, c_i32p]),
     "msa_dp_wave_counts": (ctypes.c_int32, [c_i32p, ctypes.c_int32, c_i64p, ctypes.c_int32]),
@@ -160,6 +163,14 @@ def score_bounds(lens, sub, gap):
                                    int(gap), ctypes.byref(lo), ctypes.byref(hi))
     _check(rc, "msa_dp_score_bounds")
     return lo.value, hi.value
+
+
+def check_scoring(lens, sub, gap, flags: int = 0) -> int:
+    """Status of ``msa_dp_check_scoring`` (host only: shape, scoring, mode
+    flags and the closed-form key range of that mode)."""
+    sub = np.ascontiguousarray(np.asarray(sub, dtype=np.int8))
+    return int(lib().msa_dp_check_scoring(_i32arr(lens), len(lens), sub.ctypes.data,
+                                          sub.shape[0], int(gap), int(flags)))
 
 
 def tile_edge(k: int) -> int:
@@ -451,6 +462,13 @@ class Server:
 
     def wait(self, ticket, timeout_us=-1):
         return self._result(ticket, timeout_us)
+
+    def stats(self):
+        """``{"launches", "jobs", "busy_us", "span_us", "queued"}`` so far."""
+        out = (ctypes.c_int64 * 5)()
+        _check(lib().msa_server_stats(self.h, out, 5), "msa_server_stats")
+        return dict(zip(("launches", "jobs", "busy_us", "span_us", "queued"),
+                        [int(x) for x in out]))
 
     def close(self):
         if self.h:

@@ -106,18 +106,30 @@ static int check_flags(const Plan &p, uint32_t flags) {
   return MSA_OK;
 }
 
+extern "C" int msa_dp_check_scoring(const int32_t *lens, int32_t k, const int8_t *submat,
+                                    int32_t alpha, int32_t gap, uint32_t flags) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  rc = check_flags(p, flags);
+  if (rc) return rc;
+  return check_scoring_mode(lens, k, submat, alpha, gap, flags);
+}
+
 extern "C" int msa_dp_prepare_ex(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
                                  int32_t k, const int8_t *submat, int32_t alpha, int32_t gap,
                                  uint32_t flags, void *hip_stream) {
   int rc = validate_shape(lens, k);
   if (rc) return rc;
   if (!d_workspace || ((uintptr_t)d_workspace & 255)) return MSA_EINVAL;
-  rc = check_scoring(lens, k, submat, alpha, gap);
-  if (rc) return rc;
   Plan p;
   rc = make_plan(lens, k, &p);
   if (rc) return rc;
   rc = check_flags(p, flags);
+  if (rc) return rc;
+  rc = check_scoring_mode(lens, k, submat, alpha, gap, flags);
   if (rc) return rc;
   if (ws_bytes < p.bytes) return MSA_EINVAL;
   return prepare_workspace(p, (char *)d_workspace, submat, alpha, gap, (int32_t)flags,
@@ -259,7 +271,7 @@ static int host_call_setup(const uint8_t *const *seqs, const int32_t *lens, int3
   for (int i = 0; i < k; ++i)
     for (int32_t t = 0; t < lens[i]; ++t)
       if (seqs[i][t] >= alpha) return MSA_EINVAL;
-  int rc = check_scoring(lens, k, submat, alpha, gap);
+  int rc = check_scoring_mode(lens, k, submat, alpha, gap, flags);
   if (rc) return rc;
 
   HostCache &c = g_cache;

@@ -155,26 +155,16 @@ constexpr int64_t kWaitLimitTicks = 200000000;  // 2 s
 #endif
 constexpr int kMaxNap = MSA_MAX_NAP;
 
-// Face-plane accesses and completion flags.
-//  SYNC 1: plain face loads/stores, agent-scope release fence before the flag,
-//          agent-scope acquire fence after the wait (C++ memory model).
-//  SYNC 2: face values are relaxed agent-scope atomics (device-coherent
-//          loads/stores, no cache write-back or invalidate); the flag is
-//          stored only after the wave's face stores have completed.
-template <int SYNC>
+// Face-plane accesses.  Face values are relaxed agent-scope atomics
+// (device-coherent loads and stores that bypass the non-coherent per-XCD
+// cache state); a tile's completion flag is stored only after the wave's face
+// stores have completed (see process_tile), so a reader that has seen the
+// flag reads the final face values.
 __device__ inline int32_t face_load(const int32_t *p) {
-  if constexpr (SYNC == 2)
-    return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-  else
-    return *p;
+  return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <int SYNC>
 __device__ inline void face_store(int32_t *p, int32_t v) {
-  if constexpr (SYNC == 2)
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  else
-    *p = v;
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Per-launch constant table into LDS (done once per persistent workgroup).
@@ -247,7 +237,7 @@ struct HaloSlots {
 // copied inside LDS instead of loaded, and its flag is not polled.
 // cols: column schedule; no tile reads a dimension-0 face plane, so none is
 // exported.
-template <int K, int NT, int SYNC>
+template <int K, int NT>
 __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int epoch,
                              Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm,
                              const HaloSlots<K, NT> &hs, bool egf = false,
@@ -341,6 +331,28 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     }
   }
 
+  // ---- column schedule: layer l_0 = 0 is the previous tile's last layer ----
+  // (l_0 = its extent), still in LDS.  It is copied before the dependency
+  // wait, so that the barrier after the wait orders every read and write of
+  // the copy before the halo stores below, which rewrite words of both
+  // layers (their l_i = 0 edges for i >= 1).
+  if (own0) {
+    using HS0 = HaloSlots<K, NT>;
+    const int e0 = c[0] - 1 == 0 ? 1 : T;
+#pragma unroll
+    for (int it = 0; it < HS0::IT; ++it) {
+      uint32_t w;
+      if constexpr (HS0::PRE)
+        w = hs.d[it];
+      else
+        w = HS0::compute(tid, it);
+      int s = 0;
+#pragma unroll
+      for (int j = K - 1; j >= 1; --j) s += HS0::digit(w, K - 1 - j) * C::sstride(j);
+      if ((w >> 31) == 0) sm.S[s] = sm.S[s + e0 * C::sstride(0)];
+    }
+  }
+
   // ---- wait for the k face predecessors (diagonal ones are implied) ----
   // (pruned mode: for every kept lower neighbour, lane S polling tile c - e_S)
   // Wave 0 polls: lane i reads the flag of tile c - e_i until it has seen it
@@ -388,10 +400,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     }
   }
   __syncthreads();
-  if constexpr (SYNC != 2)
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  else
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 
   MSA_TRACE_POINT(jd, tile, 1);
   // ---- halo: layer l_i = 0 along each dimension ----
@@ -415,18 +424,6 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     else
       return HS::compute(tid, it);
   };
-  if (own0) {
-    // layer l_0 = 0 is the previous tile's last layer (l_0 = its extent)
-    const int e0 = c[0] - 1 == 0 ? 1 : T;
-#pragma unroll
-    for (int it = 0; it < HS::IT; ++it) {
-      const uint32_t w = slot(it);
-      int s = 0;
-#pragma unroll
-      for (int j = K - 1; j >= 1; --j) s += HS::digit(w, K - 1 - j) * C::sstride(j);
-      if ((w >> 31) == 0) sm.S[s] = sm.S[s + e0 * C::sstride(0)];
-    }
-  }
   {
     constexpr int cnt = ipow(E, K - 1);
     constexpr int IT = (cnt + NT - 1) / NT;
@@ -466,7 +463,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
             // a cell of a pruned tile was never computed: -infinity
             const bool take = valid && !neg && ((kbits >> (src & 63)) & 1) != 0;
             // unconditional load from a clamped in-range offset, then select
-            const int32_t got = face_load<SYNC>(plane + (take ? foff : 0));
+            const int32_t got = face_load(plane + (take ? foff : 0));
             val[di][it] = take ? got : kNegKey;
           }
         }
@@ -757,7 +754,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
       for (int di = 0; di < DG; ++di)
 #pragma unroll
         for (int it = 0; it < IT; ++it)
-          if (st[di][it]) face_store<SYNC>(jd.faces + fo[di][it], val[di][it]);
+          if (st[di][it]) face_store(jd.faces + fo[di][it], val[di][it]);
     }
   }
 
@@ -767,13 +764,9 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
   // wave 0 stores the flag.  All 64 lanes of wave 0 store the same value: a
   // lane-divergent branch next to the persistent loop's back edge lets the
   // compiler peel lanes off the loop.
-  if constexpr (SYNC == 1) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  } else {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);  // the wave's face stores have completed
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);  // the wave's face stores have completed
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __syncthreads();
   if (wave == 0)
     __hip_atomic_store(jd.flags + tile, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -827,7 +820,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
 // Plain path: one job, descriptor passed by value.
 // pass (pruned mode): 1 = first pass, 2 = second pass, which runs only when
 // the first missed its threshold; 0 otherwise.
-template <int K, int NT, int SYNC>
+template <int K, int NT>
 __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
                                                   const int32_t *__restrict__ order, int pass) {
   __shared__ Smem<K> sm;
@@ -865,11 +858,11 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
     if (cols) {
       const int base = __builtin_amdgcn_readfirstlane(jd.corder[qi]);
       for (int c0 = 0; c0 < jd.P[0]; ++c0)
-        process_tile<K, NT, SYNC>(jd, alpha, gap, base + c0 * jd.tstride[0], epoch, ctrl,
+        process_tile<K, NT>(jd, alpha, gap, base + c0 * jd.tstride[0], epoch, ctrl,
                                   &ctrl->status, sm, hs, egf, &ctrl->best, coopt, false,
                                   c0 > 0, true);
     } else {
-      process_tile<K, NT, SYNC>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]),
+      process_tile<K, NT>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]),
                                 epoch, ctrl, &ctrl->status, sm, hs, egf, &ctrl->best, coopt,
                                 prune);
     }
@@ -1388,7 +1381,7 @@ __device__ void batch_column(const JobDev &jd, int base, int epoch, Ctrl *ctrl, 
   }
   const HaloSlots<K, NT> hs(threadIdx.x);
   for (int c0 = 0; c0 < jd.P[0]; ++c0)
-    process_tile<K, NT, 2>(jd, jd.alpha, jd.gap, base + c0 * jd.tstride[0], epoch, ctrl,
+    process_tile<K, NT>(jd, jd.alpha, jd.gap, base + c0 * jd.tstride[0], epoch, ctrl,
                            jd.jstatus, sm, hs, false, nullptr, false, false, c0 > 0, true);
 }
 
@@ -1473,25 +1466,11 @@ __global__ void batch_finish_kernel(Ctrl *ctrl) {
 // ---------------------------------------------------------------------------
 constexpr int kFillThreads = 256;  // four waves per tile
 
-static int g_sync_mode = -1;
-
-static int sync_mode() {
-  if (g_sync_mode < 0) {
-    const char *e = getenv("MSA_SYNC");
-    g_sync_mode = (e && atoi(e) == 1) ? 1 : 2;
-  }
-  return g_sync_mode;
-}
-
 template <int K>
 static int launch_fill_k(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid,
                          int pass, hipStream_t s) {
-  if (sync_mode() == 1)
-    hipLaunchKernelGGL((fill_kernel<K, kFillThreads, 1>), dim3(grid), dim3(kFillThreads), 0, s,
-                       jd, ctrl, order, pass);
-  else
-    hipLaunchKernelGGL((fill_kernel<K, kFillThreads, 2>), dim3(grid), dim3(kFillThreads), 0, s,
-                       jd, ctrl, order, pass);
+  hipLaunchKernelGGL((fill_kernel<K, kFillThreads>), dim3(grid), dim3(kFillThreads), 0, s, jd,
+                     ctrl, order, pass);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1504,7 +1483,7 @@ static int launch_traceback_k(const JobDev &jd, Ctrl *ctrl, hipStream_t s) {
 template <int K>
 static int occupancy_k() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fill_kernel<K, kFillThreads, 2>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fill_kernel<K, kFillThreads>,
                                                    kFillThreads, 0) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;

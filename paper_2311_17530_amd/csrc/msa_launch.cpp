@@ -77,6 +77,7 @@ Launch::~Launch() {
   if (h_in_) (void)hipHostFree(h_in_);
   if (h_out_) (void)hipHostFree(h_out_);
   if (done_) (void)hipEventDestroy(done_);
+  if (start_) (void)hipEventDestroy(start_);
   if (stream_) (void)hipStreamDestroy(stream_);
 }
 
@@ -84,7 +85,9 @@ int Launch::init(int64_t bytes) {
   if (hipGetDevice(&device_) != hipSuccess) return MSA_EDEVICE;
   if (!stream_ && hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking) != hipSuccess)
     return MSA_EDEVICE;
-  if (!done_ && hipEventCreateWithFlags(&done_, hipEventDisableTiming) != hipSuccess)
+  if (!done_ && hipEventCreateWithFlags(&done_, hipEventDefault) != hipSuccess)
+    return MSA_EDEVICE;
+  if (!start_ && hipEventCreateWithFlags(&start_, hipEventDefault) != hipSuccess)
     return MSA_EDEVICE;
   if (cap_ < bytes) {
     if (d_) (void)hipFree(d_);
@@ -290,7 +293,8 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   }
 
   // ---- enqueue ----
-  bool ok = hipMemcpyAsync(d_, h, (size_t)in_bytes, hipMemcpyHostToDevice, stream_) == hipSuccess;
+  bool ok = hipEventRecord(start_, stream_) == hipSuccess;
+  ok = ok && hipMemcpyAsync(d_, h, (size_t)in_bytes, hipMemcpyHostToDevice, stream_) == hipSuccess;
   int grid = device_cu_count() * batch_occupancy(kc);
   if (grid < 1) grid = 1;
   ok = ok && launch_batch(kc, reinterpret_cast<const JobDev *>(d_ + off_jobs), nj,
@@ -319,6 +323,11 @@ int Launch::wait() {
   if (!busy_) return MSA_OK;
   if (hipEventSynchronize(done_) != hipSuccess) launch_status_ = MSA_EDEVICE;
   return launch_status_;
+}
+
+bool Launch::interval_ms(hipEvent_t ref, float *t0, float *t1) const {
+  return hipEventElapsedTime(t0, ref, start_) == hipSuccess &&
+         hipEventElapsedTime(t1, ref, done_) == hipSuccess;
 }
 
 void Launch::result(int i, LaunchResult *out) const {

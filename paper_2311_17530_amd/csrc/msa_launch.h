@@ -58,6 +58,10 @@ class Launch {
   void result(int i, LaunchResult *out) const;
   void fill_result(int i, msa_result *out) const;
   int njobs() const { return (int)meta_.size(); }
+  // After ready()/wait(): the launch's device interval (from its first copy
+  // to its last) in milliseconds after `ref`, an event recorded earlier on
+  // the same device.  False if the events cannot be read.
+  bool interval_ms(hipEvent_t ref, float *t0, float *t1) const;
   void release() { busy_ = false; meta_.clear(); }
 
  private:
@@ -68,7 +72,8 @@ class Launch {
   };
   int device_ = -1;
   hipStream_t stream_ = nullptr;
-  hipEvent_t done_ = nullptr;
+  hipEvent_t start_ = nullptr;  // before the input copy (timing)
+  hipEvent_t done_ = nullptr;   // after the output copy (timing)
   char *d_ = nullptr;
   int64_t cap_ = 0;
   char *h_in_ = nullptr;  // pinned staging (inputs)

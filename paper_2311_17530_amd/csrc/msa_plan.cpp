@@ -188,6 +188,33 @@ int check_scoring(const int32_t *lens, int32_t k, const int8_t *submat, int32_t 
   return MSA_OK;
 }
 
+int check_scoring_mode(const int32_t *lens, int32_t k, const int8_t *submat, int32_t alpha,
+                       int32_t gap, uint32_t flags) {
+  int rc = check_scoring(lens, k, submat, alpha, gap);
+  if (rc || !(flags & kPrune)) return rc;
+  // Pruned mode: a kept tile whose lower neighbours were pruned starts from
+  // -infinity halo keys, and such values can travel along a monotone path of
+  // up to sum(n_i) cells through kept tiles, each step adding one column score
+  // (|column score| <= colmax).  They must stay below every real key (real
+  // scores are >= lo) and above the int32 minimum:
+  //   -2^30 + 2^k * sum(n) * colmax < 2^k * (lo - 1)
+  //   -2^30 - 2^k * sum(n) * colmax >= -2^31.
+  int64_t lo = 0, hi = 0;
+  rc = score_bounds(lens, k, submat, alpha, gap, &lo, &hi);
+  if (rc) return rc;
+  int64_t sum = 0;
+  for (int i = 0; i < k; ++i) sum += lens[i];
+  int sabs = 0;
+  for (int i = 0; i < alpha * alpha; ++i)
+    sabs = std::max<int>(sabs, submat[i] < 0 ? -submat[i] : submat[i]);
+  const int64_t g = gap < 0 ? -(int64_t)gap : gap;
+  const int64_t colmax = (int64_t)(k * (k - 1) / 2) * std::max<int64_t>(g, sabs);
+  const int64_t chain = sum * colmax;
+  const int64_t need = chain + (lo < 0 ? -lo : lo) + 1;
+  if (need >= (((int64_t)1 << 30) >> k)) return MSA_ERANGE;
+  return MSA_OK;
+}
+
 void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd) {
   memset(jd, 0, sizeof(*jd));
   jd->k = p.k;

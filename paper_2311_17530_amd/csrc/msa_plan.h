@@ -61,6 +61,11 @@ int check_scoring(const int32_t *lens, int32_t k, const int8_t *submat, int32_t 
 int score_bounds(const int32_t *lens, int32_t k, const int8_t *submat, int32_t alpha,
                  int32_t gap, int64_t *lo, int64_t *hi);
 
+// check_scoring plus the range the mode `flags` needs (the pruned mode's
+// -infinity chains).  Returns 0 or a negative status.
+int check_scoring_mode(const int32_t *lens, int32_t k, const int8_t *submat, int32_t alpha,
+                       int32_t gap, uint32_t flags);
+
 // Device descriptor for a plan placed at workspace base `ws`.
 void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd);
 

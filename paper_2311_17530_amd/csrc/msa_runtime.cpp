@@ -16,9 +16,17 @@ namespace msa {
 
 namespace {
 std::mutex g_mu;
-// Mode flags of each prepared workspace (by device address), so that a launch
-// knows its kernel sequence without reading the device control block.
-std::unordered_map<uintptr_t, int32_t> g_ws_flags;
+// What each prepared workspace (by device address) was prepared for: its
+// shape, so that a launch on it with other lengths is refused, and its mode
+// flags, so that a launch knows its kernel sequence without reading the
+// device control block.
+struct WsSig {
+  int32_t k = 0;
+  int32_t n[kMaxK] = {};
+  int64_t bytes = 0;
+  int32_t flags = 0;
+};
+std::unordered_map<uintptr_t, WsSig> g_ws;
 int g_cu[64] = {};
 int g_occ[64][kMaxK + 1] = {};
 }  // namespace
@@ -39,8 +47,19 @@ int device_cu_count() {
 
 int32_t workspace_flags(const char *ws) {
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_ws_flags.find((uintptr_t)ws);
-  return it == g_ws_flags.end() ? 0 : it->second;
+  auto it = g_ws.find((uintptr_t)ws);
+  return it == g_ws.end() ? 0 : it->second.flags;
+}
+
+int check_workspace(const Plan &p, const char *ws) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws.find((uintptr_t)ws);
+  if (it == g_ws.end()) return MSA_EINVAL;  // never prepared
+  const WsSig &w = it->second;
+  if (w.k != p.k || w.bytes != p.bytes) return MSA_EINVAL;
+  for (int i = 0; i < p.k; ++i)
+    if (w.n[i] != p.n[i]) return MSA_EINVAL;
+  return MSA_OK;
 }
 
 static int occupancy(int k) {
@@ -83,9 +102,16 @@ int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, 
                             hipMemcpyHostToDevice, s) == hipSuccess;
   ok = ok && hipMemsetAsync(ws + p.off_flags, 0, (size_t)p.ntiles * 4, s) == hipSuccess;
   ok = ok && hipStreamSynchronize(s) == hipSuccess;
+  std::lock_guard<std::mutex> lk(g_mu);
   if (ok) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_ws_flags[(uintptr_t)ws] = flags;
+    WsSig w;
+    w.k = p.k;
+    for (int i = 0; i < p.k; ++i) w.n[i] = p.n[i];
+    w.bytes = p.bytes;
+    w.flags = flags;
+    g_ws[(uintptr_t)ws] = w;
+  } else {
+    g_ws.erase((uintptr_t)ws);  // a failed set-up leaves the workspace unprepared
   }
   return ok ? MSA_OK : MSA_EDEVICE;
 }
@@ -123,12 +149,6 @@ static int run_fill(const Plan &p, char *ws, JobDev &jd, hipStream_t s) {
   Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
   const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
   int grid = fill_grid(p);
-  // MSA_COLUMNS=0 (tuning): the tile queue instead of the column schedule
-  static const int col_env = [] {
-    const char *e = getenv("MSA_COLUMNS");
-    return e ? atoi(e) : 1;
-  }();
-  if (!col_env) jd.ncols = 0;
   if (jd.ncols > 0 && grid > jd.ncols) grid = jd.ncols;
   if (!(workspace_flags(ws) & kPrune)) return launch_fill(jd, ctrl, order, grid, 0, s);
   PruneDev pd;
@@ -147,6 +167,7 @@ static int run_fill(const Plan &p, char *ws, JobDev &jd, hipStream_t s) {
 int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, uint8_t *d_aln,
               int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,
               int which) {
+  if (check_workspace(p, ws) != MSA_OK) return MSA_EINVAL;
   JobDev jd;
   fill_jobdev(p, ws, 0, 0, &jd);  // alpha and gap are read from the control block
   jd.seqs = d_seqs;
@@ -167,6 +188,7 @@ int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, 
 int run_coopt(const Plan &p, char *ws, const uint8_t *d_seqs, int32_t max_paths, int64_t *d_score,
               uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len, int32_t *d_npaths,
               int32_t *d_status, hipStream_t s) {
+  if (check_workspace(p, ws) != MSA_OK) return MSA_EINVAL;
   JobDev jd;
   fill_jobdev(p, ws, 0, 0, &jd);
   jd.seqs = d_seqs;
@@ -180,6 +202,7 @@ int run_coopt(const Plan &p, char *ws, const uint8_t *d_seqs, int32_t max_paths,
 }
 
 int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s) {
+  if (check_workspace(p, ws) != MSA_OK) return MSA_EINVAL;
   JobDev jd;
   fill_jobdev(p, ws, 0, 0, &jd);
   const Ctrl *ctrl = reinterpret_cast<const Ctrl *>(ws + p.off_ctrl);
@@ -192,6 +215,7 @@ namespace msa {
 
 int export_prune(const Plan &p, char *ws, uint8_t *keep_out, int64_t *info_out,
                  hipStream_t s) {
+  if (check_workspace(p, ws) != MSA_OK) return MSA_EINVAL;
   if (!p.prunable || !(workspace_flags(ws) & kPrune)) return MSA_EINVAL;
   const Ctrl *ctrl = reinterpret_cast<const Ctrl *>(ws + p.off_ctrl);
   bool ok = true;

@@ -30,6 +30,8 @@ int batch_occupancy(int kclass);
 int device_cu_count();
 // mode flags given to prepare_workspace for the workspace at `ws` (0 if none)
 int32_t workspace_flags(const char *ws);
+// MSA_OK when `ws` was prepared for the shape of `p`, else MSA_EINVAL
+int check_workspace(const Plan &p, const char *ws);
 int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, int gap,
                       int32_t flags, hipStream_t s);
 // which: 1 = fill only, 2 = traceback only, 3 = both

@@ -8,6 +8,7 @@
 // device.  Finished results wait in a table until polled.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -71,20 +72,30 @@ struct msa_server {
   std::vector<Slot> slots;
   std::thread worker;
   int init_status = MSA_OK;
+  // statistics: launches and jobs completed, and each launch's device
+  // interval (ms after `ref`, recorded at creation) for the busy time
+  hipEvent_t ref = nullptr;
+  int64_t n_launches = 0, n_jobs = 0;
+  std::vector<std::pair<float, float>> intervals;
 
   void run();
-  bool admit(Slot &s);
+  bool admit(Slot &s, int free_slots);
   void collect(Slot &s);
 };
 
-bool msa_server::admit(Slot &s) {
+bool msa_server::admit(Slot &s, int free_slots) {
   // FIFO admission: the oldest job fixes the k class; later jobs of the same
-  // class join while they fit the slot's arena and the per-launch job limit.
+  // class join while they fit the slot's arena and the launch's share of the
+  // queue: the queued jobs split evenly over the free slots (at most
+  // max_jobs each), so a short queue gives small launches that finish soon
+  // and a burst spreads over every free slot instead of filling one.
   if (queue.empty()) return false;
   const int kc = kclass_of(queue.front()->job.k);
+  const int64_t share = ((int64_t)queue.size() + free_slots - 1) / std::max(1, free_slots);
+  const int limit = (int)std::min<int64_t>(max_jobs, std::max<int64_t>(1, share));
   std::vector<const msa_job *> grp;
   int64_t used = 0, tiles = 0;
-  for (auto it = queue.begin(); it != queue.end() && (int)grp.size() < max_jobs;) {
+  for (auto it = queue.begin(); it != queue.end() && (int)grp.size() < limit;) {
     Pending &p = **it;
     if (kclass_of(p.job.k) != kc) {
       ++it;
@@ -127,6 +138,10 @@ bool msa_server::admit(Slot &s) {
 
 void msa_server::collect(Slot &s) {
   s.launch->wait();
+  float t0 = 0.f, t1 = 0.f;
+  if (ref && s.launch->interval_ms(ref, &t0, &t1)) intervals.emplace_back(t0, t1);
+  ++n_launches;
+  n_jobs += (int64_t)s.tickets.size();
   for (size_t i = 0; i < s.tickets.size(); ++i) {
     LaunchResult r;
     s.launch->result((int)i, &r);
@@ -160,8 +175,13 @@ void msa_server::run() {
         progress = true;
       }
     }
+    int free_slots = 0;
+    for (auto &s : slots) free_slots += s.launch->busy() ? 0 : 1;
     for (auto &s : slots) {
-      if (!s.launch->busy() && !queue.empty() && !stop) progress |= admit(s);
+      if (!s.launch->busy() && !queue.empty() && !stop) {
+        progress |= admit(s, free_slots);
+        --free_slots;
+      }
     }
     bool any_busy = false;
     for (auto &s : slots) any_busy |= s.launch->busy();
@@ -195,6 +215,9 @@ extern "C" msa_server *msa_server_create(int64_t hbm_budget_bytes, int32_t max_i
     sl.launch.reset(new Launch());
     if (sl.launch->init(s->slot_bytes) != MSA_OK) return nullptr;
   }
+  if (hipEventCreate(&s->ref) != hipSuccess || hipEventRecord(s->ref, nullptr) != hipSuccess ||
+      hipEventSynchronize(s->ref) != hipSuccess)
+    return nullptr;
   s->worker = std::thread([p = s.get()] { p->run(); });
   return s.release();
 }
@@ -280,6 +303,38 @@ extern "C" int msa_server_wait(msa_server *srv, uint64_t ticket, msa_result *out
   return take_result(srv, ticket, out);
 }
 
+extern "C" int msa_server_stats(msa_server *srv, int64_t *out, int32_t n) {
+  if (!srv || !out || n < 1) return MSA_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  // union of the launches' device intervals: time with at least one launch
+  // of this server on the device
+  std::vector<std::pair<float, float>> iv = srv->intervals;
+  std::sort(iv.begin(), iv.end());
+  double busy = 0.0, lo = 0.0, hi = 0.0, first = 0.0, last = 0.0;
+  bool open = false;
+  for (auto &x : iv) {
+    if (!open) {
+      lo = x.first;
+      hi = x.second;
+      first = x.first;
+      open = true;
+    } else if (x.first > hi) {
+      busy += hi - lo;
+      lo = x.first;
+      hi = x.second;
+    } else if (x.second > hi) {
+      hi = x.second;
+    }
+    last = std::max(last, (double)x.second);
+  }
+  if (open) busy += hi - lo;
+  const int64_t v[5] = {srv->n_launches, srv->n_jobs, (int64_t)(busy * 1000.0),
+                        open ? (int64_t)((last - first) * 1000.0) : 0,
+                        (int64_t)srv->queue.size()};
+  for (int i = 0; i < n && i < 5; ++i) out[i] = v[i];
+  return MSA_OK;
+}
+
 extern "C" void msa_server_destroy(msa_server *srv) {
   if (!srv) return;
   {
@@ -288,5 +343,6 @@ extern "C" void msa_server_destroy(msa_server *srv) {
     srv->cv_work.notify_all();
   }
   if (srv->worker.joinable()) srv->worker.join();
+  if (srv->ref) (void)hipEventDestroy(srv->ref);
   delete srv;
 }

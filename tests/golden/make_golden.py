@@ -27,7 +27,7 @@ import numpy as np
 ROOT = Path(__file__).resolve().parents[2]
 sys.path.insert(0, str(ROOT))
 
-from msa_inputs import dna_scoring, workload  # noqa: E402
+from msa_inputs import batch_jobs, dna_scoring, workload  # noqa: E402
 from oracle import oracle_align  # noqa: E402
 from oracle.brute import brute_force_align  # noqa: E402
 
@@ -90,6 +90,27 @@ def workload_cases(names):
         path.write_text(json.dumps(doc, indent=1) + "\n")
 
 
+def batch_largest_case():
+    """The largest job of the 4096-job batch (by cells): the oracle's score
+    and row hash, for the batched-path test (the other jobs are compared with
+    the plain path, itself pinned to the oracle's full decision tensors)."""
+    path = HERE / "workloads.json"
+    doc = json.loads(path.read_text())
+    jobs = batch_jobs(4096)
+    idx = int(np.argmax([j.cells for j in jobs]))
+    job = jobs[idx]
+    t0 = time.time()
+    score, rows, _ = oracle_align(job.seqs, job.sub, job.gap)
+    dt = time.time() - t0
+    doc["batch_4096_largest"] = dict(
+        job_index=idx, k=job.k, lens=job.lens, cells=job.cells, score=score,
+        aln_len=int(rows.shape[1]),
+        rows_sha256=hashlib.sha256(np.ascontiguousarray(rows).tobytes()).hexdigest(),
+        oracle_seconds=round(dt, 2))
+    print("batch_4096_largest", idx, job.lens, score, rows.shape, round(dt, 1), "s", flush=True)
+    path.write_text(json.dumps(doc, indent=1) + "\n")
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--full", action="store_true")
@@ -101,3 +122,5 @@ if __name__ == "__main__":
         names = [n for n in ("dna_k3_40", "prot_k3_512", "prot_k4_128")
                  if a.only is None or n in a.only]
         workload_cases(names)
+        if a.only is None or "batch_largest" in a.only:
+            batch_largest_case()

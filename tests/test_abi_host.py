@@ -212,3 +212,60 @@ def test_prune_workspace_holds_pair_tables():
     base = msa.workspace_bytes([40, 33])  # k = 2: no pruning area
     assert msa.workspace_bytes(lens) >= extra + ntiles * ((T ** 3 + 15) // 16 * 16)
     assert base > 0
+
+
+def test_pruned_range_covers_minus_infinity_chains():
+    # Pruned mode: -infinity halo keys (-2^30) of a kept tile cut off from the
+    # origin travel along monotone paths of up to sum(n) cells, one column
+    # score (|.| <= colmax = C(k,2) * max(|gap|, max|sub|)) per step, and must
+    # stay below every real key (scores >= lo).  The check therefore needs
+    # 2^k * (sum(n) * colmax + |lo| + 1) < 2^30 on top of the plain check.
+    k = 6
+    sub = np.full((4, 4), -127, np.int8)
+    np.fill_diagonal(sub, 127)
+    gap = -127
+    colmax = comb(k, 2) * 127
+    # four empty sequences keep the tile grid small; sum(n) is what counts
+    for a, fits in ((3302, True), (3303, False)):
+        lens = [a, 3303, 0, 0, 0, 0]
+        lo, _ = msa.score_bounds(lens, sub, gap)
+        need = (2 ** k) * (sum(lens) * colmax + abs(lo) + 1)
+        assert (need < 2 ** 30) == fits
+        assert msa.check_scoring(lens, sub, gap, 0) == msa.MSA_OK  # plain mode fits both
+        want = msa.MSA_OK if fits else msa.MSA_ERANGE
+        assert msa.check_scoring(lens, sub, gap, msa.MSA_PRUNE) == want
+    # the same range through the entry point that prepares a workspace: the
+    # check runs before the (unallocated) workspace is touched
+    lens6 = (ctypes_i32(6))(3303, 3303, 0, 0, 0, 0)
+    rc = msa.lib().msa_dp_prepare_ex(256, 1 << 40, lens6, k,
+                                     np.ascontiguousarray(sub).ctypes.data, 4, gap,
+                                     msa.MSA_PRUNE, None)
+    assert rc == msa.MSA_ERANGE
+
+
+def ctypes_i32(n):
+    import ctypes
+    return ctypes.c_int32 * n
+
+
+def test_unprepared_or_mismatched_workspace_rejected_before_device():
+    # every device-buffer entry point checks that the workspace was prepared
+    # for the same shape before it enqueues anything
+    import ctypes
+    lib = msa.lib()
+    fake = 1 << 20  # an aligned address no call has prepared
+    lens = (ctypes.c_int32 * 3)(5, 6, 7)
+    dummy = ctypes.c_void_p(1 << 21)
+    rc = lib.msa_dp_align_dev(fake, 1 << 30, dummy, lens, 3, dummy, dummy, 64, dummy, dummy,
+                              None)
+    assert rc == msa.MSA_EINVAL
+    rc = lib.msa_dp_fill_dev(fake, 1 << 30, dummy, lens, 3, dummy, None)
+    assert rc == msa.MSA_EINVAL
+    rc = lib.msa_dp_traceback_dev(fake, 1 << 30, dummy, lens, 3, dummy, dummy, 64, dummy, dummy,
+                                  None)
+    assert rc == msa.MSA_EINVAL
+    rc = lib.msa_dp_export_dirs(fake, 1 << 30, lens, 3, dummy, None)
+    assert rc == msa.MSA_EINVAL
+    rc = lib.msa_dp_coopt_dev(fake, 1 << 30, dummy, lens, 3, 1, dummy, dummy, 64, dummy, dummy,
+                              dummy, None)
+    assert rc == msa.MSA_EINVAL

@@ -169,3 +169,24 @@ def test_full_size_workloads_against_stored_oracle(name):
     assert hashlib.sha256(np.ascontiguousarray(rows).tobytes()).hexdigest() == gold["rows_sha256"]
     d = dev.export_dirs()
     assert hashlib.sha256(np.ascontiguousarray(d).tobytes()).hexdigest() == gold["dir_sha256"]
+
+
+def test_workspace_prepared_for_other_lengths_is_refused():
+    # a workspace prepared for one shape: a call with other lengths (that
+    # need no more bytes) returns MSA_EINVAL at once and enqueues nothing
+    import ctypes
+    from paper_2311_17530_amd._lib import _i32arr
+    sub, gap = dna_scoring()
+    dev = msa.DeviceAligner([20, 20, 20], sub, gap)
+    dev.set_sequences([np.zeros(20, np.uint8)] * 3)
+    dev.run()
+    s0, _ = dev.result()
+    other = [19, 20, 21]
+    assert msa.workspace_bytes(other) <= dev.ws_bytes
+    rc = msa.lib().msa_dp_align_dev(dev.ws_ptr, dev.ws_bytes, dev.d_seqs.data_ptr(),
+                                    _i32arr(other), 3, dev.d_score.data_ptr(),
+                                    dev.d_aln.data_ptr(), dev.cap, dev.d_len.data_ptr(),
+                                    dev.d_status.data_ptr(), ctypes.c_void_p(dev._stream()))
+    assert rc == msa.MSA_EINVAL
+    dev.run()  # the prepared shape still runs
+    assert dev.result()[0] == s0
