@@ -202,6 +202,27 @@ int msa_dp_align_dev(void *d_workspace, int64_t ws_bytes,
                      int64_t *d_score, uint8_t *d_aln, int64_t aln_cap,
                      int64_t *d_aln_len, int32_t *d_status, void *hip_stream);
 
+/* msa_dp_align_static: msa_dp_align_dev without a caller workspace, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The call allocates
+ * nothing: the workspace is a file-scope device array of 32 MiB that each
+ * device the library runs on holds until the process ends, and its set-up
+ * (control block, matrix, column schedule, cleared flags) is a kernel whose
+ * inputs come by value, so the call only enqueues kernels on hip_stream
+ * (asynchronous).  Arguments as msa_dp_align_dev, plus the scoring of
+ * msa_dp_prepare (submat is a host pointer read during the call).
+ * Limits: alpha <= 32 and a workspace (msa_dp_workspace_bytes) of at most
+ * 32 MiB -- MSA_EINVAL / MSA_ENOMEM otherwise, returned at once with nothing
+ * enqueued; the other errors as msa_dp_align_dev.  Plain mode only.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (the set-up rewrites what must start cleared): calls that
+ * overlap on one device race and must be ordered by the caller (one stream,
+ * or events between streams). */
+int msa_dp_align_static(const uint8_t *d_seqs, const int32_t *lens, int32_t k,
+                        const int8_t *submat, int32_t alpha, int32_t gap,
+                        int64_t *d_score, uint8_t *d_aln, int64_t aln_cap,
+                        int64_t *d_aln_len, int32_t *d_status, void *hip_stream);
+
 /* The two launches of msa_dp_align_dev, for callers that time or overlap them
  * separately.  msa_dp_fill_dev scores every cell and writes the optimal score
  * to d_score; msa_dp_traceback_dev then writes the alignment, its length and

@@ -78,6 +78,9 @@ _SIGS = {
                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32, c_vp]),
     "msa_dp_align_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p, ctypes.c_int32,
                                         c_vp, c_vp, ctypes.c_int64, c_vp, c_vp, c_vp]),
+    "msa_dp_align_static": (ctypes.c_int, [c_vp, c_i32p, ctypes.c_int32, c_vp, ctypes.c_int32,
+                                           ctypes.c_int32, c_vp, c_vp, ctypes.c_int64, c_vp,
+                                           c_vp, c_vp]),
     "msa_dp_fill_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p, ctypes.c_int32,
                                        c_vp, c_vp]),
     "msa_dp_traceback_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p,

@@ -168,6 +168,12 @@ int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, 
               int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,
               int which) {
   if (check_workspace(p, ws) != MSA_OK) return MSA_EINVAL;
+  return run_plain_set_up(p, ws, d_seqs, d_score, d_aln, aln_cap, d_aln_len, d_status, s, which);
+}
+
+int run_plain_set_up(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score,
+                     uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status,
+                     hipStream_t s, int which) {
   JobDev jd;
   fill_jobdev(p, ws, 0, 0, &jd);  // alpha and gap are read from the control block
   jd.seqs = d_seqs;

@@ -38,6 +38,12 @@ int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, 
 int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, uint8_t *d_aln,
               int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,
               int which = 3);
+// run_plain on a workspace whose set-up the caller guarantees (plain mode,
+// no registry check): the allocation-free entry point sets its static
+// workspace up on the device itself.
+int run_plain_set_up(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score,
+                     uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status,
+                     hipStream_t s, int which = 3);
 int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s);
 // pruned mode: keep flags of the last pass (ntiles bytes, row-major tile
 // index) and {U, threshold, tiles kept, passes} of the last fill
