@@ -289,10 +289,13 @@ class _Marshalled:
                 "latency_ms_p99": round(float(np.percentile(lat, 99)), 3)}
 
 
+TRAFFIC_SOURCES = ("msa_sweep3.hip", "msa_plan.cpp", "msa_runtime.cpp")
+
+
 def measured_traffic():
     """HBM bytes per launch of the k=3 fill from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, calibrated against a device copy), or
-    None when the kernel or launch sources changed since it was taken."""
+    None when the kernel, plan or launch sources changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "fill_k3_prot512_hbm_traffic.md")
     try:
@@ -300,11 +303,11 @@ def measured_traffic():
     except OSError:
         return None
     h = hashlib.sha256()
-    for f in ("msa_kernels.hip", "msa_runtime.cpp"):
+    for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_2311_17530_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     vals = dict(ln.split(": ", 1) for ln in text.splitlines() if ": " in ln and not ln.startswith(" "))
-    if vals.get("source_sha256 (msa_kernels.hip + msa_runtime.cpp)") != h.hexdigest():
+    if vals.get("source_sha256 (" + " + ".join(TRAFFIC_SOURCES) + ")") != h.hexdigest():
         return None
     return int(vals["traffic_bytes_per_launch"])
 
@@ -357,11 +360,15 @@ def sclk_during(fn, seconds=0.4):
 
     import torch
     stop = threading.Event()
+    errors = []
 
     def spin():
-        while not stop.is_set():
-            fn()
-            torch.cuda.synchronize()
+        try:
+            while not stop.is_set():
+                fn()
+                torch.cuda.synchronize()
+        except Exception as exc:  # noqa: BLE001 -- re-raised below
+            errors.append(exc)
 
     th = threading.Thread(target=spin)
     th.start()
@@ -375,6 +382,8 @@ def sclk_during(fn, seconds=0.4):
     finally:
         stop.set()
         th.join()
+    if errors:
+        raise errors[0]
     for card in data.values():
         if isinstance(card, dict):
             for key, val in card.items():
@@ -392,7 +401,7 @@ def _sclk_main():
     job = workload(MAIN)
     dev = msa.DeviceAligner(job.lens, job.sub, job.gap)
     dev.set_sequences(job.seqs)
-    return sclk_during(dev.run_fill)
+    return sclk_during(dev.run)  # whole alignments: a fill is always followed by its traceback
 
 
 def copy_probe(nbytes, steps):
@@ -415,6 +424,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-clock", action="store_true",
+                    help="skip the shader-clock reading (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (counter calibration)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-job batch")
@@ -477,13 +488,14 @@ def main():
                      "algorithmic_bytes": main_r["cells"],
                      "algorithmic_hbm_frac": round(main_r["cells"] / fill_s / 1e9 / PEAK_HBM_GBS,
                                                    4),
-                     "kernel": "fill_kernel<3,256,2> (k=3, T=16, one line per lane)",
+                     "kernel": "sweep3_kernel (k=3 streaming fill: 8 rows x 64 lanes per "
+                               "workgroup, one workgroup per CU)",
                      "ops_per_launch": 2 * main_r["neighbour_updates"]},
         "extra": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                       for kk, vv in v.items()} for k, v in extra.items()},
     }
     line["host"] = host_cpu()
-    line["sclk_mhz_during_fill"] = _sclk_main()
+    line["sclk_mhz_during_fill"] = None if a.no_clock else _sclk_main()
     if not a.no_batched:
         line["batched"] = bench_batched()
     if not a.no_served:

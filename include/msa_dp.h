@@ -227,7 +227,9 @@ int msa_dp_align_static(const uint8_t *d_seqs, const int32_t *lens, int32_t k,
  * separately.  msa_dp_fill_dev scores every cell and writes the optimal score
  * to d_score; msa_dp_traceback_dev then writes the alignment, its length and
  * the status (and resets d_score to 0 on error).  Same arguments and rules as
- * msa_dp_align_dev; the traceback must follow the fill on the same stream. */
+ * msa_dp_align_dev; the traceback must follow the fill on the same stream:
+ * it re-arms the workspace's work counter, so a second fill without the
+ * traceback in between finds no work left and returns without scoring. */
 int msa_dp_fill_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
                     const int32_t *lens, int32_t k, int64_t *d_score, void *hip_stream);
 

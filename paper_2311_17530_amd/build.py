@@ -27,7 +27,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
           "-Wno-unused-but-set-variable"]
 
-SOURCES = ["msa_kernels.hip", "msa_prune.hip", "msa_static.hip", "msa_plan.cpp", "msa_launch.cpp",
+SOURCES = ["msa_kernels.hip", "msa_sweep3.hip", "msa_prune.hip", "msa_static.hip", "msa_plan.cpp", "msa_launch.cpp",
            "msa_runtime.cpp", "msa_abi.cpp", "msa_batch.cpp", "msa_server.cpp"]
 
 

@@ -120,6 +120,15 @@ constexpr int kSelBlock = 1024;
 constexpr int kCoMaxK = 3;
 constexpr int kCoMaxTotal = 32768;
 
+// Streaming fill of k = 3 (msa_sweep3.hip): a workgroup owns kSwNW rows
+// (dimension 0) x 64 lanes (dimension 1) of lines along dimension 2 and
+// sweeps the whole length; neighbouring workgroups exchange their boundary
+// lines through tagged values in two exchange regions of the workspace.
+constexpr int kSwNW = 8;           // compute waves (rows) per workgroup
+constexpr int kSwLanes = 64;       // lanes (dimension-1 cells) per wave
+constexpr int kSwSeqMax = 16384;   // longest third sequence (kept in LDS)
+constexpr int kSwSubMax = 32;      // largest alphabet (matrix kept in LDS)
+
 // One entry of the batched tile queue: (job index, tile linear index).
 struct QItem {
   int32_t job;

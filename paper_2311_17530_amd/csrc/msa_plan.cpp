@@ -112,9 +112,24 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
     q.off_korder = o; o = align256(o + q.ntiles * 4);
     q.off_bcnt = o;   o = align256(o + (int64_t)q.nblocks * 4);
   }
+  if (k == 3) {
+    q.sw_nb0 = (q.n[0] + 1 + kSwNW - 1) / kSwNW;
+    q.sw_nb1 = (q.n[1] + 1 + kSwLanes - 1) / kSwLanes;
+    q.x0_plane = ((int64_t)q.n[1] + q.n[2] + 1) * ((int64_t)q.n[1] + 1);
+    q.x1_plane = ((int64_t)q.n[0] + 1) * ((int64_t)q.n[2] + 1);
+    q.off_x0 = o;
+    o = align256(o + std::max<int64_t>((q.sw_nb0 - 1) * q.x0_plane * 4, 256));
+    q.off_x1 = o;
+    o = align256(o + std::max<int64_t>((q.sw_nb1 - 1) * q.x1_plane * 4, 256));
+    q.x_bytes = o - q.off_x0;
+  }
   q.bytes = o;
   *p = q;
   return MSA_OK;
+}
+
+bool sweep3_eligible(const Plan &p, int alpha, int32_t flags) {
+  return p.k == 3 && flags == 0 && alpha >= 1 && alpha <= kSwSubMax && p.n[2] <= kSwSeqMax;
 }
 
 void make_tile_order(const Plan &p, std::vector<int32_t> *order) {

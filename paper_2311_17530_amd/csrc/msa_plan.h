@@ -38,7 +38,17 @@ struct Plan {
   int64_t tab_off[kMaxPairs] = {}, bm_off[kMaxPairs] = {};  // int32 elements
   int32_t nblocks = 0;
   int64_t off_ptab = 0, off_pbm = 0, off_keep = 0, off_korder = 0, off_bcnt = 0;
+  // streaming fill of k = 3: workgroup grid and the two exchange regions,
+  // X0 (last row of each workgroup row, by diagonal d = v1 + v2) and X1 (last
+  // lane of each workgroup column)
+  int32_t sw_nb0 = 0, sw_nb1 = 0;
+  int64_t x0_plane = 0, x1_plane = 0;  // int32 elements per boundary
+  int64_t off_x0 = 0, off_x1 = 0, x_bytes = 0;
 };
+
+// The streaming k = 3 fill runs the plain mode (flags 0) of a k = 3 plan
+// whose alphabet and third sequence fit its LDS tables.
+bool sweep3_eligible(const Plan &p, int alpha, int32_t flags);
 
 constexpr int64_t kSubBytes = 255 * 255;
 constexpr int64_t kMaxTiles = (int64_t)1 << 30;

@@ -25,6 +25,7 @@ struct WsSig {
   int32_t n[kMaxK] = {};
   int64_t bytes = 0;
   int32_t flags = 0;
+  int32_t alpha = 0;
 };
 std::unordered_map<uintptr_t, WsSig> g_ws;
 int g_cu[64] = {};
@@ -51,7 +52,7 @@ int32_t workspace_flags(const char *ws) {
   return it == g_ws.end() ? 0 : it->second.flags;
 }
 
-int check_workspace(const Plan &p, const char *ws) {
+int check_workspace(const Plan &p, const char *ws, int32_t *alpha) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_ws.find((uintptr_t)ws);
   if (it == g_ws.end()) return MSA_EINVAL;  // never prepared
@@ -59,6 +60,7 @@ int check_workspace(const Plan &p, const char *ws) {
   if (w.k != p.k || w.bytes != p.bytes) return MSA_EINVAL;
   for (int i = 0; i < p.k; ++i)
     if (w.n[i] != p.n[i]) return MSA_EINVAL;
+  if (alpha) *alpha = w.alpha;
   return MSA_OK;
 }
 
@@ -101,6 +103,9 @@ int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, 
   ok = ok && hipMemcpyAsync(ws + p.off_corder, corder.data(), corder.size() * 4,
                             hipMemcpyHostToDevice, s) == hipSuccess;
   ok = ok && hipMemsetAsync(ws + p.off_flags, 0, (size_t)p.ntiles * 4, s) == hipSuccess;
+  // the streaming k = 3 fill's exchange regions: tag 0, never a launch's tag
+  if (p.k == 3)
+    ok = ok && hipMemsetAsync(ws + p.off_x0, 0, (size_t)p.x_bytes, s) == hipSuccess;
   ok = ok && hipStreamSynchronize(s) == hipSuccess;
   std::lock_guard<std::mutex> lk(g_mu);
   if (ok) {
@@ -109,6 +114,7 @@ int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, 
     for (int i = 0; i < p.k; ++i) w.n[i] = p.n[i];
     w.bytes = p.bytes;
     w.flags = flags;
+    w.alpha = alpha;
     g_ws[(uintptr_t)ws] = w;
   } else {
     g_ws.erase((uintptr_t)ws);  // a failed set-up leaves the workspace unprepared
@@ -145,8 +151,9 @@ static int fill_grid(const Plan &p) {
 // The fill of a prepared workspace: one launch, or in pruned mode (the mode
 // is known to the host from the plan and flags cached at set-up) the bound,
 // selection and two-pass sequence of msa_prune.hip.
-static int run_fill(const Plan &p, char *ws, JobDev &jd, hipStream_t s) {
+static int run_fill(const Plan &p, char *ws, JobDev &jd, hipStream_t s, int alpha) {
   Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
+  if (sweep3_eligible(p, alpha, workspace_flags(ws))) return launch_sweep3(p, ws, jd, ctrl, s);
   const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
   int grid = fill_grid(p);
   if (jd.ncols > 0 && grid > jd.ncols) grid = jd.ncols;
@@ -167,13 +174,15 @@ static int run_fill(const Plan &p, char *ws, JobDev &jd, hipStream_t s) {
 int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, uint8_t *d_aln,
               int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status, hipStream_t s,
               int which) {
-  if (check_workspace(p, ws) != MSA_OK) return MSA_EINVAL;
-  return run_plain_set_up(p, ws, d_seqs, d_score, d_aln, aln_cap, d_aln_len, d_status, s, which);
+  int32_t alpha = 0;
+  if (check_workspace(p, ws, &alpha) != MSA_OK) return MSA_EINVAL;
+  return run_plain_set_up(p, ws, alpha, d_seqs, d_score, d_aln, aln_cap, d_aln_len, d_status, s,
+                          which);
 }
 
-int run_plain_set_up(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score,
-                     uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status,
-                     hipStream_t s, int which) {
+int run_plain_set_up(const Plan &p, char *ws, int alpha, const uint8_t *d_seqs,
+                     int64_t *d_score, uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len,
+                     int32_t *d_status, hipStream_t s, int which) {
   JobDev jd;
   fill_jobdev(p, ws, 0, 0, &jd);  // alpha and gap are read from the control block
   jd.seqs = d_seqs;
@@ -186,7 +195,7 @@ int run_plain_set_up(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_
   jd.trace = g_trace_buf;
 #endif
   Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
-  if ((which & 1) && run_fill(p, ws, jd, s) != 0) return MSA_EDEVICE;
+  if ((which & 1) && run_fill(p, ws, jd, s, alpha) != 0) return MSA_EDEVICE;
   if ((which & 2) && launch_traceback(jd, ctrl, s) != 0) return MSA_EDEVICE;
   return MSA_OK;
 }
@@ -194,7 +203,8 @@ int run_plain_set_up(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_
 int run_coopt(const Plan &p, char *ws, const uint8_t *d_seqs, int32_t max_paths, int64_t *d_score,
               uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len, int32_t *d_npaths,
               int32_t *d_status, hipStream_t s) {
-  if (check_workspace(p, ws) != MSA_OK) return MSA_EINVAL;
+  int32_t alpha = 0;
+  if (check_workspace(p, ws, &alpha) != MSA_OK) return MSA_EINVAL;
   JobDev jd;
   fill_jobdev(p, ws, 0, 0, &jd);
   jd.seqs = d_seqs;
@@ -202,13 +212,13 @@ int run_coopt(const Plan &p, char *ws, const uint8_t *d_seqs, int32_t max_paths,
   jd.aln_cap = aln_cap;
   jd.status_out = d_status;
   Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
-  if (run_fill(p, ws, jd, s) != 0) return MSA_EDEVICE;
+  if (run_fill(p, ws, jd, s, alpha) != 0) return MSA_EDEVICE;
   if (launch_coopt(jd, ctrl, max_paths, d_aln, d_aln_len, d_npaths, s) != 0) return MSA_EDEVICE;
   return MSA_OK;
 }
 
 int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s) {
-  if (check_workspace(p, ws) != MSA_OK) return MSA_EINVAL;
+  if (check_workspace(p, ws, nullptr) != MSA_OK) return MSA_EINVAL;
   JobDev jd;
   fill_jobdev(p, ws, 0, 0, &jd);
   const Ctrl *ctrl = reinterpret_cast<const Ctrl *>(ws + p.off_ctrl);
@@ -221,7 +231,7 @@ namespace msa {
 
 int export_prune(const Plan &p, char *ws, uint8_t *keep_out, int64_t *info_out,
                  hipStream_t s) {
-  if (check_workspace(p, ws) != MSA_OK) return MSA_EINVAL;
+  if (check_workspace(p, ws, nullptr) != MSA_OK) return MSA_EINVAL;
   if (!p.prunable || !(workspace_flags(ws) & kPrune)) return MSA_EINVAL;
   const Ctrl *ctrl = reinterpret_cast<const Ctrl *>(ws + p.off_ctrl);
   bool ok = true;

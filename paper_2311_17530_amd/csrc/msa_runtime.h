@@ -25,13 +25,16 @@ int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_j
                  int32_t *qjob, int32_t *qtile, int64_t tiles, int64_t cols, int32_t *flags,
                  Ctrl *ctrl, int grid, hipStream_t s);
 int batch_occupancy(int kclass);
+// streaming k = 3 fill (msa_sweep3.hip), for plans with sweep3_eligible
+int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, hipStream_t s);
 
 // runtime (msa_runtime.cpp)
 int device_cu_count();
 // mode flags given to prepare_workspace for the workspace at `ws` (0 if none)
 int32_t workspace_flags(const char *ws);
-// MSA_OK when `ws` was prepared for the shape of `p`, else MSA_EINVAL
-int check_workspace(const Plan &p, const char *ws);
+// MSA_OK when `ws` was prepared for the shape of `p` (and its alphabet size
+// in *alpha when alpha is not null), else MSA_EINVAL
+int check_workspace(const Plan &p, const char *ws, int32_t *alpha);
 int prepare_workspace(const Plan &p, char *ws, const int8_t *submat, int alpha, int gap,
                       int32_t flags, hipStream_t s);
 // which: 1 = fill only, 2 = traceback only, 3 = both
@@ -41,9 +44,9 @@ int run_plain(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score, 
 // run_plain on a workspace whose set-up the caller guarantees (plain mode,
 // no registry check): the allocation-free entry point sets its static
 // workspace up on the device itself.
-int run_plain_set_up(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t *d_score,
-                     uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len, int32_t *d_status,
-                     hipStream_t s, int which = 3);
+int run_plain_set_up(const Plan &p, char *ws, int alpha, const uint8_t *d_seqs,
+                     int64_t *d_score, uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len,
+                     int32_t *d_status, hipStream_t s, int which = 3);
 int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s);
 // pruned mode: keep flags of the last pass (ntiles bytes, row-major tile
 // index) and {U, threshold, tiles kept, passes} of the last fill

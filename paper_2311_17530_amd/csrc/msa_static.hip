@@ -17,6 +17,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "../../include/msa_dp.h"
@@ -116,6 +117,14 @@ __global__ __launch_bounds__(256) void static_setup_kernel(JobDev jd, Ctrl *ctrl
   }
 }
 
+// Clears `n` int32 words (the streaming k = 3 fill's exchange regions: tag 0
+// is never a launch's tag).
+__global__ __launch_bounds__(256) void static_zero_kernel(int32_t *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 }  // namespace msa
 
 using namespace msa;
@@ -160,6 +169,11 @@ extern "C" int msa_dp_align_static(const uint8_t *d_seqs, const int32_t *lens, i
                      reinterpret_cast<uint8_t *>(ws + p.off_sub),
                      reinterpret_cast<int32_t *>(ws + p.off_flags),
                      reinterpret_cast<int32_t *>(ws + p.off_corder), a);
+  if (k == 3) {
+    const int64_t words = p.x_bytes / 4;
+    hipLaunchKernelGGL(static_zero_kernel, dim3((unsigned)std::min<int64_t>(1024, words / 256 + 1)),
+                       dim3(256), 0, s, reinterpret_cast<int32_t *>(ws + p.off_x0), words);
+  }
   if (hipGetLastError() != hipSuccess) return MSA_EDEVICE;
-  return run_plain_set_up(p, ws, d_seqs, d_score, d_aln, aln_cap, d_aln_len, d_status, s);
+  return run_plain_set_up(p, ws, alpha, d_seqs, d_score, d_aln, aln_cap, d_aln_len, d_status, s);
 }

@@ -1,0 +1,522 @@
+// msa_sweep3.hip -- streaming fill of the three-sequence tensor.
+//
+// The cells of one computation wave (Section 3: cells, or partitions, at
+// equal distance from the origin are independent) are the hyperplane
+// v0 + v1 + v2 = h.  This kernel sweeps those hyperplanes in a pipeline
+// instead of tile by tile:
+//
+//   - Lines.  A line is the run of cells (v0, v1, 0..n2) along dimension 2.
+//     A workgroup owns kSwNW x 64 lines: rows v0 = B0*kSwNW + w (wave w) and
+//     columns v1 = B1*64 + j (lane j), and sweeps them over the whole length
+//     in steps: at block step s, lane j of wave w computes cell t = s - j - w
+//     of its line.  Every neighbour v - b of that cell was computed by the
+//     same lane, the lane to its left (v1 - 1) or the wave above (v0 - 1) one
+//     to three steps earlier, so a step needs no wait beyond one barrier.
+//   - Exchange inside a wave: lane j - 1's previous output arrives by a DPP
+//     wave shift (wave_shr:1); outputs of two steps back are kept in
+//     registers.  Between waves: each wave writes its outputs to an LDS ring
+//     of 4 steps, read by the wave below one or two steps later.  Entry 0 of
+//     a ring row is the value of the row's lane -1 (the workgroup to the
+//     left), so every lane reads its neighbours at fixed offsets.
+//   - Exchange between workgroups: the outputs of the last wave go to region
+//     X0 and those of lane 63 of every wave to region X1, each value tagged
+//     with the launch's epoch in its low 3 bits (keys keep those bits clear).
+//     A loader wave (wave kSwNW) does every global access of the exchange:
+//     it stores this workgroup's boundary outputs one step after they are
+//     computed, and loads the neighbours' values kSwPf steps ahead, checks
+//     their tags (reloading while any is stale) and writes them to LDS one
+//     step before they are read.  Compute waves issue no global load, and
+//     their only stores (direction bytes, every 16 steps) are never waited on.
+//   - Workgroups take tickets in order of their block diagonal B0 + B1; a
+//     workgroup only waits for workgroups with smaller tickets, which are
+//     already running, so the grid cannot deadlock.
+//
+// Per cell (Section 2, Eq. 1 for three sequences; Section 4 per-cell steps):
+// seven candidates key(v - b) + column(b), the column score being the sum of
+// the pair scores of the residues the mask b takes plus gap * 2 for a one- or
+// two-residue column, all pre-shifted by 3 bits with the tie bits 7 - b in
+// the low bits, so one signed maximum gives the score and, among equal
+// scores, the lowest mask.  Direction bytes are stored in the same
+// tile-major blocks (edge 16) as the tile kernel's, so the traceback, the
+// decision export and the other modes read them unchanged: each lane keeps
+// the bytes of its current and previous 16-cell run in LDS, and every 16
+// steps the whole wave stores the runs completed since.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "msa_internal.h"
+#include "msa_plan.h"
+
+namespace msa {
+
+namespace {
+
+constexpr int kSwRing = 4;        // LDS rings (outputs, halo rows): 4 steps
+constexpr int kSwPf = 8;          // loader prefetch distance (steps)
+constexpr int kSwUnroll = 16;     // steps per unrolled group (direction flush)
+constexpr int kSwRow = 65;        // ring row: the lane-(-1) entry + 64 lanes
+constexpr int kSwSeqPad = 128;    // LDS bytes around the third sequence
+constexpr int kSwThreads = (kSwNW + 1) * 64;
+constexpr int kSwT = 16;          // tile edge of the direction blocks (k = 3)
+constexpr int kSwDbs = kSwT * kSwT * kSwT;
+constexpr int64_t kSwWaitTicks = 200000000;  // 2 s of the 100 MHz clock
+
+static_assert(kSwDbs == 4096, "direction blocks of edge 16");
+static_assert(tile_edge_for_k(3) == kSwT, "same blocks as the tile kernel");
+static_assert(kSwUnroll % kSwRing == 0 && kSwUnroll % kSwPf == 0, "ring slots fixed per group");
+
+struct Sweep3Dev {
+  int32_t n0, n1, n2;
+  int32_t nb0, nb1;           // workgroups along dimensions 0 and 1
+  const uint8_t *s0, *s1, *s2;
+  const int8_t *sub;
+  int32_t *x0;                // X0[b][d][v1], b < nb0 - 1, d = v1 + v2
+  int64_t x0_plane;
+  int32_t *x1;                // X1[b][v0][v2], b < nb1 - 1
+  int64_t x1_plane;
+  uint8_t *dir;               // tile-major direction blocks
+  int32_t ts0, ts1;           // tile strides of dimensions 0 and 1 (dimension 2: 1)
+  int64_t *score_out;
+  int64_t *trace;             // debug builds: 8 words per workgroup ticket
+};
+
+struct SwSmem {
+  int32_t ring[kSwRing][kSwNW][kSwRow];    // row w of step s: slot s % 4
+  int32_t in0[kSwRing][kSwRow];            // the row above the workgroup (wave -1)
+  int32_t junk[64];                        // loader lanes without a halo value write here
+  int32_t sub8[kSwSubMax * kSwSubMax];     // substitution matrix << 3
+  alignas(16) uint8_t stage[kSwNW][64][32];  // per lane: two 16-cell runs
+  uint8_t s2[kSwSeqPad + kSwSeqMax + kSwSeqPad];
+  int32_t ticket;
+};
+
+// LDS writes of this wave complete, then every wave of the workgroup meets.
+// Global stores stay in flight: no wave waits on them.
+__device__ __forceinline__ void sw_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+__device__ __forceinline__ int32_t sw_load(const int32_t *p) {
+  return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void sw_store(int32_t *p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The loader wave.  During step s it writes step s + 1's halo to LDS:
+//   - the row above: in0[s % 4] entry i = cell (B0*kSwNW - 1, B1*64 - 1 + i,
+//     s + 2 - i) = X0[B0-1][B1*64 + s + 1][B1*64 - 1 + i] (element 0 of lane
+//     i; entry 64 is element 1 of lane 0);
+//   - lane -1 of each row w: ring[(s + 1) % 4][w][0] = cell (B0*kSwNW + w,
+//     B1*64 - 1, s + 2 - w) = X1[B1-1][B0*kSwNW + w][s + 2 - w] (element 1
+//     of lane 1 + w);
+// and issues the loads of step s + kSwPf.  A cell outside the tensor, or
+// without a workgroup before this one, reads -infinity.  Every lane issues
+// both loads every step (an address clamped into its element's window of
+// cells, or a dummy word), so the wait for a step's values counts exactly the
+// younger loads.
+struct SwLoader {
+  // Element x of step s is the word at wbase[x] + (s - llo[x]) * linc[x], a
+  // cell for s - llo[x] in [0, span].  acc[x] = (s - llo[x]) * linc[x] for
+  // the next step to issue (steps are issued in order, one per call); an
+  // element with no cell has linc 0 and acc -1.
+  const int32_t *wbase[2];
+  int32_t acc[2], linc[2], ohi[2], lag[2];  // ohi = span * linc, lag = kSwPf * linc
+  int32_t dst1[kSwRing];  // LDS word index (in the ring array) of element 1, per slot s % 4
+
+  __device__ void set(int x, const int32_t *base, int llo, int inc, int span, int s_first) {
+    wbase[x] = base;
+    linc[x] = inc;
+    acc[x] = (s_first - llo) * inc;
+    ohi[x] = span * inc;
+    lag[x] = kSwPf * inc;
+  }
+
+  __device__ SwLoader(const Sweep3Dev &sd, SwSmem &sm, int B0, int B1, int lane,
+                      const int32_t *dummy, int s_first) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      wbase[x] = dummy;
+      acc[x] = -1;
+      linc[x] = 0;
+      ohi[x] = 0;
+      lag[x] = 0;
+    }
+    // element 0: in0 entry lane, cells for s in [lane - 2, n2 + lane - 2]
+    {
+      const int v1 = B1 * kSwLanes - 1 + lane;
+      if (B0 > 0 && v1 >= 0 && v1 <= sd.n1)
+        set(0, sd.x0 + (int64_t)(B0 - 1) * sd.x0_plane +
+                   (int64_t)(B1 * kSwLanes + lane - 1) * (sd.n1 + 1) + v1,
+            lane - 2, sd.n1 + 1, sd.n2, s_first);
+    }
+    // element 1: in0 entry 64 (lane 0) or lane -1 of row lane - 1
+    const int32_t *const rbase = &sm.ring[0][0][0];
+#pragma unroll
+    for (int k = 0; k < kSwRing; ++k) dst1[k] = (int32_t)(&sm.junk[lane] - rbase);
+    if (lane == 0) {
+      const int v1 = B1 * kSwLanes + 63;
+#pragma unroll
+      for (int k = 0; k < kSwRing; ++k) dst1[k] = (int32_t)(&sm.in0[k][64] - rbase);
+      if (B0 > 0 && v1 <= sd.n1)
+        set(1, sd.x0 + (int64_t)(B0 - 1) * sd.x0_plane +
+                   (int64_t)(B1 * kSwLanes + 63) * (sd.n1 + 1) + v1,
+            62, sd.n1 + 1, sd.n2, s_first);
+    } else if (lane <= kSwNW) {
+      const int w = lane - 1;
+      const int v0 = B0 * kSwNW + w;
+#pragma unroll
+      for (int k = 0; k < kSwRing; ++k)
+        dst1[k] = (int32_t)(&sm.ring[(k + 1) & (kSwRing - 1)][w][0] - rbase);
+      if (B1 > 0 && v0 <= sd.n0)
+        set(1, sd.x1 + (int64_t)(B1 - 1) * sd.x1_plane + (int64_t)v0 * (sd.n2 + 1),
+            w - 2, 1, sd.n2, s_first);
+    }
+  }
+
+  // the word of element x at window offset a, clamped into the window
+  __device__ __forceinline__ const int32_t *addr(int x, int32_t a) const {
+    return wbase[x] + (uint32_t)min(max(a, 0), ohi[x]);
+  }
+
+  __device__ __forceinline__ void issue(int32_t (&v)[2]) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      v[x] = sw_load(addr(x, acc[x]));
+      acc[x] += linc[x];
+    }
+  }
+
+  // some value of a step (window offsets a) is a cell's and not yet this
+  // launch's
+  __device__ __forceinline__ bool stale(const int32_t (&a)[2], const int32_t (&v)[2],
+                                        int tag) const {
+    int st = 0;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+      st |= (int)((unsigned)a[x] <= (unsigned)ohi[x]) & (int)((v[x] & 7) != tag);
+    return __builtin_amdgcn_ballot_w64(st != 0) != 0;
+  }
+
+  // Slow path: reloads the values (into registers of its own) until every
+  // one carries this launch's tag or the watchdog fires.
+  __device__ __forceinline__ void respin(const int32_t (&a)[2], int32_t (&v)[2], int tag,
+                                         Ctrl *ctrl, int64_t t0) const {
+    int32_t u[2];
+    for (int it = 0;; ++it) {
+      __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+      for (int x = 0; x < 2; ++x) u[x] = sw_load(addr(x, a[x]));
+      if (!stale(a, u, tag)) break;
+      if ((it & 15) == 15) {
+        const int st = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (st == -4) break;  // another workgroup timed out: stop waiting
+        if ((int64_t)wall_clock64() - t0 > kSwWaitTicks) {
+          atomicCAS(&ctrl->status, 0, -4);
+          break;
+        }
+      }
+    }
+    v[0] = u[0];
+    v[1] = u[1];
+  }
+
+  // The values of step s, issued `back` steps before the next one to issue
+  // (reloaded while any carries another launch's tag), to LDS.  The first
+  // check is straight-line code, so its wait counts only the younger loads.
+  __device__ __forceinline__ void finish(int s, int back, int32_t (&v)[2], int tag, SwSmem &sm,
+                                         int lane, Ctrl *ctrl, int64_t t0, int &nspin) const {
+    int32_t a[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) a[x] = acc[x] - (back == kSwPf ? lag[x] : back * linc[x]);
+    if (stale(a, v, tag)) {
+      respin(a, v, tag, ctrl, t0);
+      ++nspin;
+    }
+    const bool r0 = (unsigned)a[0] <= (unsigned)ohi[0];
+    const bool r1 = (unsigned)a[1] <= (unsigned)ohi[1];
+    sm.in0[s & (kSwRing - 1)][lane] = r0 ? (v[0] & ~7) : kNegKey;
+    (&sm.ring[0][0][0])[dst1[s & (kSwRing - 1)]] = r1 ? (v[1] & ~7) : kNegKey;
+  }
+};
+
+// One compute wave: row v0 = B0*kSwNW + w, lane j: column v1 = B1*64 + j.
+// kX0: the last row of a workgroup with one below it (stores X0); kX1: a row
+// of a workgroup with one to its right (lane 63 stores X1); kOrigin: wave 0
+// of workgroup (0, 0), whose lane 0 holds the origin.
+template <bool kX0, bool kX1, bool kOrigin>
+__device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B0, int B1, int w,
+                                          int j, bool lane_ok, int r0, int r1, int gap, int tag,
+                                          int total) {
+  const int v0 = B0 * kSwNW + w;
+  const int v1 = B1 * kSwLanes + j;
+  const int g16 = gap * 16;  // (gap * 2 column pairs) << 3
+  const int32_t K1 = g16 + 6, K2 = g16 + 5, K4 = g16 + 3;
+  const int32_t p01 = sm.sub8[r0 * kSwSubMax + r1];
+  const int32_t C3 = p01 + g16 + 4, K5 = g16 + 2, K6 = g16 + 1;
+  // direction bytes: tile (c0, c1, c2), line q0 * 16 + q1, byte q2
+  const int c0 = v0 == 0 ? 0 : (v0 - 1) / kSwT + 1, q0 = v0 == 0 ? 0 : (v0 - 1) % kSwT;
+  const int c1 = v1 == 0 ? 0 : (v1 - 1) / kSwT + 1, q1 = v1 == 0 ? 0 : (v1 - 1) % kSwT;
+  uint8_t *const dline =
+      sd.dir + ((int64_t)c0 * sd.ts0 + (int64_t)c1 * sd.ts1) * kSwDbs + (q0 * kSwT + q1) * kSwT;
+  uint8_t *const stage = &sm.stage[w][j][0];
+  const int n2 = sd.n2;
+  // rows of the wave above: the loader's in0 for wave 0, else the ring
+  const int32_t *const prow = (w == 0 ? &sm.in0[0][0] : &sm.ring[0][w - 1][0]) + j;
+  const int pstride = w == 0 ? kSwRow : kSwNW * kSwRow;
+  const int32_t *const sub_r0 = sm.sub8 + r0 * kSwSubMax;
+  const int32_t *const sub_r1 = sm.sub8 + r1 * kSwSubMax;
+  const int jw = j + w;
+  // exchange stores: cell (v0, v1, t) of the last row at X0[B0][v1 + t][v1]
+  // (v1 + t = B1*64 + s - w); lane 63's cell at X1[B1][v0][t] (t = s - 63 - w)
+  int32_t *const x0b = sd.x0 + (int64_t)B0 * sd.x0_plane +
+                       (int64_t)(B1 * kSwLanes - w) * (sd.n1 + 1) + v1;
+  const int64_t x0inc = sd.n1 + 1;
+  int32_t *const x1b = sd.x1 + (int64_t)B1 * sd.x1_plane + (int64_t)v0 * (sd.n2 + 1) - (63 + w);
+  const bool lane63 = j == 63;
+
+  int32_t outp = kNegKey;   // own output of the previous step (cell t - 1)
+  int32_t b5 = kNegKey, b6 = kNegKey, b7 = kNegKey;
+  int32_t hcur = sm.ring[kSwRing - 1][w][0];  // lane -1 at t = -w (step -1)
+  // pair scores of the third residue one step ahead (they do not depend on
+  // the scores), and its code two steps ahead; s2_j[s] is the residue of t
+  const uint8_t *s2_j = sm.s2 + kSwSeqPad - 1 - jw;
+  int32_t p02n = sub_r0[s2_j[0]];
+  int32_t p12n = sub_r1[s2_j[0]];
+  int r2n = s2_j[1];
+  for (int s0 = 0; s0 < total; s0 += kSwUnroll) {
+#pragma unroll
+    for (int i = 0; i < kSwUnroll; ++i) {
+      const int s = s0 + i;
+      const int t = s - jw;
+      const bool valid = lane_ok && (unsigned)t <= (unsigned)n2;
+      const int32_t p02 = p02n;
+      const int32_t p12 = p12n;
+      p02n = sub_r0[r2n];
+      p12n = sub_r1[r2n];
+      r2n = s2_j[s + 2];
+      // neighbours from the row above: (v0-1, v1, t) and (v0-1, v1-1, t)
+      const int32_t b1 = prow[((i - 1) & (kSwRing - 1)) * pstride + 1];
+      const int32_t b3 = prow[((i - 2) & (kSwRing - 1)) * pstride];
+      const int32_t hnext = sm.ring[i & (kSwRing - 1)][w][0];
+      // (v0, v1-1, t): lane j-1's previous output; lane 0 takes lane -1's
+      const int32_t b2 = __builtin_amdgcn_update_dpp(hcur, outp, 0x138, 0xF, 0xF, false);
+      const int32_t c1 = b1 + K1;
+      const int32_t c2 = b2 + K2;
+      const int32_t c3 = b3 + C3;
+      const int32_t c4 = outp + K4;
+      const int32_t c5 = b5 + p02 + K5;
+      const int32_t c6 = b6 + p12 + K6;
+      const int32_t c7 = b7 + p01 + (p02 + p12);
+      int32_t best = max(max(max(c1, c2), c3), max(max(max(c4, c5), c6), c7));
+      // the origin takes key 7: score 0, and the byte decodes to mask 0
+      if constexpr (kOrigin) best = (j == 0 && t == 0) ? 7 : best;
+      const int32_t out = valid ? (best & ~7) : kNegKey;
+      sm.ring[i & (kSwRing - 1)][w][j + 1] = out;
+      // direction byte of cell t at (t - 1) mod 32 (see the flush below)
+      stage[(t - 1) & 31] = (uint8_t)best;
+      if constexpr (kX0) {
+        if (valid) sw_store(x0b + (int64_t)s * x0inc, out | tag);
+      }
+      if constexpr (kX1) {
+        if (valid && lane63) sw_store(x1b + s, out | tag);
+      }
+      b5 = b1;
+      b6 = b2;
+      b7 = b3;
+      outp = out;
+      hcur = hnext;
+      sw_barrier();
+    }
+    // ---- direction runs completed in the last 16 steps ----
+    // Run c (cells 16c - 15 .. 16c) sits at half (c - 1) & 1 of the lane's
+    // 32 bytes, cell 0 at byte 31.  The flush after cell t = tf runs once per
+    // 16 cells, so a run is stored before any later cell reaches its half;
+    // cells past n2 only touch the tail of the last run (bytes of no cell)
+    // or halves that are never stored again.
+    if (lane_ok) {
+      const int tf = s0 + kSwUnroll - 1 - jw;
+      if (tf >= 0 && tf < 16) dline[0] = stage[31];  // cell t = 0 (its own block)
+      const int c = tf >> 4;                         // run c: cells 16c - 15 .. 16c
+      if (c >= 1 && 16 * c <= n2)
+        *reinterpret_cast<uint4 *>(dline + (int64_t)c * kSwDbs) =
+            *reinterpret_cast<const uint4 *>(stage + ((c - 1) & 1) * 16);
+      const int cl = (n2 >> 4) + 1;                  // the last, partial run
+      if ((n2 & 15) != 0 && tf >= n2 && tf - 15 <= n2)
+        *reinterpret_cast<uint4 *>(dline + (int64_t)cl * kSwDbs) =
+            *reinterpret_cast<const uint4 *>(stage + ((cl - 1) & 1) * 16);
+    }
+  }
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *ctrl) {
+  __shared__ SwSmem sm;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid) >> 6;
+  const int j = tid & 63;
+  const int alpha = ctrl->alpha;
+  const int gap = ctrl->gap;
+  const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int tag = (epoch - 1) % 7 + 1;
+
+  // ---- ticket: workgroups in order of their block diagonal B0 + B1 ----
+  if (tid == 0) sm.ticket = atomicAdd(&ctrl->head, 1);
+  // ---- tables: matrix << 3, third sequence with zero padding ----
+  bool bad = false;
+  for (int e = tid; e < alpha * alpha; e += kSwThreads)
+    sm.sub8[(e / alpha) * kSwSubMax + e % alpha] = (int32_t)sd.sub[e] * 8;
+  for (int x = tid; x < kSwSeqPad + sd.n2 + kSwSeqPad; x += kSwThreads) {
+    const int q = x - kSwSeqPad;
+    int r = (q >= 0 && q < sd.n2) ? (int)sd.s2[q] : 0;
+    bad = bad || r >= alpha;
+    sm.s2[x] = (uint8_t)(r >= alpha ? 0 : r);
+  }
+  // the rings before step 0 hold cells t < 0: -infinity
+  for (int e = tid; e < kSwRing * kSwNW * kSwRow; e += kSwThreads)
+    (&sm.ring[0][0][0])[e] = kNegKey;
+  sw_barrier();
+  const int ticket = __builtin_amdgcn_readfirstlane(sm.ticket);
+  // A ticket past the grid means the counter was not reset since the last
+  // fill (a fill must be followed by its traceback): nothing to do.
+  if (ticket >= sd.nb0 * sd.nb1) return;
+  int T = ticket;
+  int B0 = 0, B1 = 0;
+  for (int a = 0; a <= sd.nb0 + sd.nb1 - 2; ++a) {  // diagonals B0 + B1 = a
+    const int lo = a - (sd.nb1 - 1) > 0 ? a - (sd.nb1 - 1) : 0;
+    const int hi = a < sd.nb0 - 1 ? a : sd.nb0 - 1;
+    const int cnt = hi - lo + 1;
+    if (T < cnt) {
+      B0 = lo + T;
+      B1 = a - B0;
+      break;
+    }
+    T -= cnt;
+  }
+  const int nsteps = sd.n2 + 1 + 63 + (kSwNW - 1);
+  const int total = (nsteps + kSwUnroll - 1) / kSwUnroll * kSwUnroll;
+
+  if (wave == kSwNW) {
+    // ---------------- loader wave ----------------
+    if (bad) atomicCAS(&ctrl->status, 0, -1);
+    SwLoader ld(sd, sm, B0, B1, j, reinterpret_cast<const int32_t *>(ctrl), -2);
+    // the score: the corner's cell t = n2 is lane jc of wave wc at step sc
+    const bool cblock = B0 == sd.n0 / kSwNW && B1 == sd.n1 / kSwLanes;
+    const int wc = sd.n0 % kSwNW, jc = sd.n1 % kSwLanes;
+    const int sc = sd.n2 + jc + wc;
+    const int64_t t0 = (int64_t)wall_clock64();
+    int nspin = 0;
+    {
+      // the halo of steps -1 (rows -2 / -1's lane -1) and 0, then steps 1 ..
+      // kSwPf in flight
+      int32_t a[2], b[2];
+      ld.issue(a);
+      ld.issue(b);
+      ld.finish(-2, 2, a, tag, sm, j, ctrl, t0, nspin);
+      ld.finish(-1, 1, b, tag, sm, j, ctrl, t0, nspin);
+    }
+    int32_t q[kSwPf][2];
+#pragma unroll
+    for (int i = 0; i < kSwPf; ++i) ld.issue(q[i]);
+    sw_barrier();
+#ifdef MSA_TRACE
+    const int64_t t1 = (int64_t)wall_clock64();
+#endif
+    for (int s0 = 0; s0 < total; s0 += kSwUnroll) {
+#pragma unroll
+      for (int i = 0; i < kSwUnroll; ++i) {
+        const int s = s0 + i;
+        // during step s: step s + 1's halo (loaded kSwPf steps ago)
+        ld.finish(s, kSwPf, q[i % kSwPf], tag, sm, j, ctrl, t0, nspin);
+        if (cblock && s == sc + 1)
+          *sd.score_out = (int64_t)(sm.ring[sc & (kSwRing - 1)][wc][jc + 1] >> 3);
+        sw_barrier();
+        ld.issue(q[i % kSwPf]);  // step s + kSwPf
+      }
+    }
+#ifdef MSA_TRACE
+    if (sd.trace && j == 0) {
+      int64_t *tr = sd.trace + (int64_t)ticket * 8;
+      tr[0] = B0;
+      tr[1] = B1;
+      tr[2] = t0;
+      tr[3] = t1;
+      tr[4] = (int64_t)wall_clock64();
+      tr[5] = nspin;
+      tr[6] = total;
+    }
+#endif
+    return;
+  }
+
+  // ---------------- compute waves ----------------
+  const int w = wave;
+  const int v0 = B0 * kSwNW + w;
+  const int v1 = B1 * kSwLanes + j;
+  const bool row_ok = v0 <= sd.n0;
+  const bool lane_ok = row_ok && v1 <= sd.n1;
+  int r0 = (row_ok && v0 >= 1) ? (int)sd.s0[v0 - 1] : 0;
+  int r1 = (lane_ok && v1 >= 1) ? (int)sd.s1[v1 - 1] : 0;
+  bad = bad || r0 >= alpha || r1 >= alpha;
+  if (bad) atomicCAS(&ctrl->status, 0, -1);
+  r0 = __builtin_amdgcn_readfirstlane(r0 >= alpha ? 0 : r0);
+  r1 = r1 >= alpha ? 0 : r1;
+  const bool x0 = w == kSwNW - 1 && B0 < sd.nb0 - 1 && row_ok;
+  const bool x1 = B1 < sd.nb1 - 1 && row_ok;
+  sw_barrier();  // the loader's halo of steps -1 and 0 is in LDS
+  if (B0 == 0 && B1 == 0 && w == 0) {
+    if (x1)
+      sweep_row<false, true, true>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+    else
+      sweep_row<false, false, true>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+  } else if (x0 && x1)
+    sweep_row<true, true, false>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+  else if (x0)
+    sweep_row<true, false, false>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+  else if (x1)
+    sweep_row<false, true, false>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+  else
+    sweep_row<false, false, false>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+}
+
+int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, hipStream_t s) {
+  Sweep3Dev sd;
+  sd.n0 = p.n[0];
+  sd.n1 = p.n[1];
+  sd.n2 = p.n[2];
+  sd.nb0 = p.sw_nb0;
+  sd.nb1 = p.sw_nb1;
+  sd.s0 = jd.seqs;
+  sd.s1 = jd.seqs + p.n[0];
+  sd.s2 = jd.seqs + p.n[0] + p.n[1];
+  sd.sub = jd.sub;
+  sd.x0 = reinterpret_cast<int32_t *>(ws + p.off_x0);
+  sd.x0_plane = p.x0_plane;
+  sd.x1 = reinterpret_cast<int32_t *>(ws + p.off_x1);
+  sd.x1_plane = p.x1_plane;
+  sd.dir = jd.dir;
+  sd.ts0 = p.tstride[0];
+  sd.ts1 = p.tstride[1];
+  sd.score_out = jd.score_out;
+  sd.trace = jd.trace;
+  // One workgroup per CU: a second one would share the SIMDs and stretch the
+  // steps of both, and every step sits on the sweep's critical path.  The
+  // launch asks for unused LDS beyond half of a CU's.
+  int dev = 0, lds_cu = 0, lds_wg = 0;
+  size_t pad = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+          hipSuccess &&
+      hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
+    const size_t want = (size_t)lds_cu / 2 + 1024;
+    if (want > sizeof(SwSmem) && want <= (size_t)lds_wg) pad = want - sizeof(SwSmem);
+  }
+  const int grid = p.sw_nb0 * p.sw_nb1;
+  hipLaunchKernelGGL(sweep3_kernel, dim3(grid), dim3(kSwThreads), pad, s, sd, ctrl);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace msa

@@ -181,7 +181,7 @@ def test_workspace_prepared_for_other_lengths_is_refused():
     dev.set_sequences([np.zeros(20, np.uint8)] * 3)
     dev.run()
     s0, _ = dev.result()
-    other = [19, 20, 21]
+    other = [20, 19, 20]
     assert msa.workspace_bytes(other) <= dev.ws_bytes
     rc = msa.lib().msa_dp_align_dev(dev.ws_ptr, dev.ws_bytes, dev.d_seqs.data_ptr(),
                                     _i32arr(other), 3, dev.d_score.data_ptr(),
@@ -190,3 +190,89 @@ def test_workspace_prepared_for_other_lengths_is_refused():
     assert rc == msa.MSA_EINVAL
     dev.run()  # the prepared shape still runs
     assert dev.result()[0] == s0
+
+
+def test_streaming_k3_block_edges():
+    # The k=3 fill streams lines of 8 rows x 64 lanes per workgroup: rows and
+    # lanes that end one before, on and one after a workgroup edge, several
+    # workgroups per dimension, long and empty third sequences, and a gap > 0
+    # (candidate keys that grow) -- every cell's decision compared.
+    rng = np.random.Generator(np.random.PCG64(2600))
+    for lens in ([7, 63, 20], [8, 64, 21], [9, 65, 5], [23, 130, 40], [40, 129, 90],
+                 [1, 200, 15], [70, 1, 30], [15, 62, 300], [0, 64, 64], [16, 0, 9],
+                 [31, 127, 0]):
+        protein = bool(sum(lens) % 2)
+        sub, gap = protein_scoring() if protein else dna_scoring()
+        seqs = [rng.integers(0, sub.shape[0], size=n).astype(np.uint8) for n in lens]
+        check_device(seqs, sub, gap)
+    m = rng.integers(-5, 6, size=(4, 4))
+    sub = (np.triu(m) + np.triu(m, 1).T).astype(np.int8)
+    seqs = [rng.integers(0, 4, size=n).astype(np.uint8) for n in (25, 70, 33)]
+    check_device(seqs, sub, 2)
+    # cell (9, 64, 0) takes mask 3 from the left workgroup's halo entry of
+    # the row above at t = 0 (wave 1, lane 0, the ring slot before step 0)
+    r5 = np.random.Generator(np.random.PCG64(5))
+    sub, gap = protein_scoring()
+    seqs = [r5.integers(0, 20, size=n).astype(np.uint8) for n in (10, 66, 1)]
+    check_device(seqs, sub, gap)
+
+
+def test_streaming_k3_repeated_launches_and_new_sequences():
+    # Exchange values carry the launch's epoch: repeated launches on one
+    # workspace, with new sequences of the same shape in between, each equal
+    # to the oracle.
+    rng = np.random.Generator(np.random.PCG64(2700))
+    sub, gap = protein_scoring()
+    lens = [33, 100, 50]
+    dev = msa.DeviceAligner(lens, sub, gap)
+    for rep in range(9):
+        seqs = [rng.integers(0, 20, size=n).astype(np.uint8) for n in lens]
+        say("launch", rep)
+        dev.set_sequences(seqs)
+        dev.run()
+        s1, r1 = dev.result()
+        s0, r0, _ = oracle_align(seqs, sub, gap)
+        assert s1 == s0 and np.array_equal(r1, r0)
+
+
+@pytest.mark.parametrize("which", [0, 1, 2])
+def test_streaming_k3_detects_bad_code(which):
+    # A residue code >= alpha in any of the three sequences makes the k=3
+    # fill report MSA_EINVAL; the workspace stays usable afterwards.
+    rng = np.random.Generator(np.random.PCG64(2800 + which))
+    sub, gap = dna_scoring()
+    lens = [20, 70, 30]
+    seqs = [rng.integers(0, 4, size=n).astype(np.uint8) for n in lens]
+    dev = msa.DeviceAligner(lens, sub, gap)
+    bad = [s.copy() for s in seqs]
+    bad[which][lens[which] // 2] = 7
+    dev.set_sequences(bad)
+    dev.run()
+    with pytest.raises(msa.MsaError) as e:
+        dev.result()
+    assert e.value.status == msa.MSA_EINVAL
+    dev.set_sequences(seqs)
+    dev.run()
+    s, r = dev.result()
+    s0, r0, _ = oracle_align(seqs, sub, gap)
+    assert s == s0 and np.array_equal(r, r0)
+
+
+def test_second_fill_without_traceback_finds_no_work():
+    # The traceback re-arms the work counter; a fill launched twice in a row
+    # finds no work the second time and ends, and the next whole alignment is
+    # correct again.
+    rng = np.random.Generator(np.random.PCG64(2900))
+    sub, gap = protein_scoring()
+    for lens in ([30, 90, 40], [20, 20, 20, 20]):
+        seqs = [rng.integers(0, 20, size=n).astype(np.uint8) for n in lens]
+        dev = msa.DeviceAligner(lens, sub, gap)
+        dev.set_sequences(seqs)
+        say("double fill", lens)
+        dev.run_fill()
+        dev.run_fill()
+        dev.run_traceback()
+        dev.run()
+        s, r = dev.result()
+        s0, r0, _ = oracle_align(seqs, sub, gap)
+        assert s == s0 and np.array_equal(r, r0)
