@@ -184,10 +184,13 @@ def bench_served(n_jobs=20000, rates=SERVED_RATES, max_inflight=4, max_jobs=256,
         for i in range(32):  # warm-up: arenas, code load
             srv.wait(srv.submit(jobs[i].seqs, jobs[i].sub, jobs[i].gap))
         st0 = srv.stats()
-        wall, submit_s, ok = pre.run_saturated(srv)
+        wall, submit_s, status = pre.run_saturated(srv)
         st1 = srv.stats()
         busy = (st1["busy_us"] - st0["busy_us"]) / 1e6
-        out.update({"ok": ok, "saturated_jobs_per_s": round(n_jobs / wall, 2),
+        ok = int((status == 0).sum())
+        failed = {str(int(c)): int((status == c).sum()) for c in np.unique(status) if c != 0}
+        out.update({"ok": ok, "failed_by_status": failed,
+                    "saturated_jobs_per_s": round(n_jobs / wall, 2),
                     "saturated_gcups": round(cells / wall / 1e9, 3),
                     "saturated_seconds": round(wall, 4),
                     "submit_seconds": round(submit_s, 4),
@@ -275,7 +278,7 @@ class _Marshalled:
 
     def run_saturated(self, srv):
         start, _, t_done, status, submit_s = self._go(srv, None)
-        return float(t_done.max() - start), submit_s, int((status == 0).sum())
+        return float(t_done.max() - start), submit_s, status
 
     def run_stream(self, srv, rate):
         from msa_inputs import poisson_arrivals
@@ -284,6 +287,8 @@ class _Marshalled:
         span = t_done.max() - start
         lat = (t_done - t_sub) * 1e3
         return {"arrival_rate_per_s": rate, "ok": int((status == 0).sum()),
+                "failed_by_status": {str(int(c)): int((status == c).sum())
+                                     for c in np.unique(status) if c != 0},
                 "jobs_per_s": round(self.n / span, 2),
                 "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
                 "latency_ms_p99": round(float(np.percentile(lat, 99)), 3)}
