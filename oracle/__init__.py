@@ -9,8 +9,9 @@ package never imports the GPU library.
   of the paper generalised to 2^k - 1 neighbours (Section 2) with the
   sum-of-pairs column score of Section 5.2.
   ``msa_oracle_align_egf`` is the end-gap-free reading of the traceback start
-  ("highest score on the bottom edges", Section 2); ``msa_oracle_coopt``
-  enumerates co-optimal alignments (Section 6).
+  (the best cell of the far boundary, Section 2); ``msa_oracle_coopt``
+  enumerates co-optimal alignments and ``msa_oracle_nearopt`` the
+  alignments within a threshold of the optimum (Section 6).
 - ``brute.py``      enumeration of every alignment of tiny inputs, scored
   column by column; the exact optimum and the tie rule by definition.
 """
@@ -21,5 +22,6 @@ from .oracle import (  # noqa: F401
     oracle_align_egf,
     oracle_coopt,
     oracle_fill,
+    oracle_nearopt,
     oracle_lib_path,
 )

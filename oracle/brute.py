@@ -163,3 +163,27 @@ def brute_force_optima(seqs, sub, gap):
                     rows[i].append(GAP)
         out.append(rows)
     return best, out
+
+
+def brute_force_within(seqs, sub, gap, delta):
+    """Every alignment scoring at least best - ``delta``, in the enumeration
+    order above.  Returns ``(best_score, [(score, rows), ...])`` with rows as
+    k lists of codes (GAP for gaps)."""
+    all_ = list(enumerate_alignments(seqs, sub, gap))
+    best = max(s for s, _ in all_)
+    k = len(seqs)
+    out = []
+    for score, masks in all_:
+        if score < best - delta:
+            continue
+        pos = [0] * k
+        rows = [[] for _ in range(k)]
+        for b in reversed(masks):
+            for i in range(k):
+                if (b >> i) & 1:
+                    rows[i].append(int(seqs[i][pos[i]]))
+                    pos[i] += 1
+                else:
+                    rows[i].append(GAP)
+        out.append((score, rows))
+    return best, out

@@ -460,3 +460,107 @@ int msa_oracle_coopt(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
   free(path);
   return 0;
 }
+
+int msa_oracle_nearopt(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                       int32_t alpha, const int32_t *sub, int32_t gap, int64_t delta,
+                       int32_t max_paths, int64_t *score_out, int64_t *scores_out,
+                       uint8_t *aln_out, int64_t aln_cap, int64_t *aln_len_out,
+                       int32_t *npaths_out) {
+  if (validate(k, lens, seqs, alpha, sub) != 0 || delta < 0 || max_paths < 1) return -1;
+  if (!score_out || !scores_out || !aln_out || !aln_len_out || !npaths_out) return -1;
+  int64_t total = 0;
+  for (int i = 0; i < k; ++i) total += lens[i];
+  if (aln_cap < total) return -1;
+  int64_t stride[MSA_ORACLE_MAX_K];
+  int64_t ncell = 1;
+  for (int i = k - 1; i >= 0; --i) {
+    stride[i] = ncell;
+    ncell *= (int64_t)lens[i] + 1;
+  }
+  int64_t *xi = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+  uint8_t *D = (uint8_t *)malloc((size_t)ncell);
+  int *path = (int *)malloc((size_t)(total + 1) * sizeof(int));           /* mask per depth */
+  int64_t *sfx = (int64_t *)malloc((size_t)(total + 1) * sizeof(int64_t)); /* score so far */
+  if (!xi || !D || !path || !sfx) {
+    free(xi);
+    free(D);
+    free(path);
+    free(sfx);
+    return -1;
+  }
+  fill(k, lens, seqs, alpha, sub, gap, xi, D);
+  const int64_t threshold = xi[ncell - 1] - delta;
+  const int nmask = 1 << k;
+
+  /* depth-first walk from the far corner: path[d] is the mask taken at depth
+   * d, sfx[d] the score of the columns taken before depth d */
+  int64_t lin = ncell - 1;
+  int64_t d = 0;
+  int32_t np = 0;
+  path[0] = 0;
+  sfx[0] = 0;
+  int64_t v[MSA_ORACLE_MAX_K];
+  int col[MSA_ORACLE_MAX_K];
+  for (;;) {
+    if (lin == 0) { /* reached the origin: emit the alignment of path[0..d) */
+      uint8_t *blk = aln_out + (int64_t)np * k * aln_cap;
+      int64_t pos[MSA_ORACLE_MAX_K];
+      for (int i = 0; i < k; ++i) pos[i] = 0;
+      for (int64_t c = 0; c < d; ++c) { /* columns origin first */
+        const int b = path[d - 1 - c];
+        for (int i = 0; i < k; ++i)
+          blk[i * aln_cap + c] = ((b >> i) & 1) ? seqs[i][pos[i]++] : MSA_ORACLE_GAP;
+      }
+      aln_len_out[np] = d;
+      scores_out[np] = sfx[d];
+      if (++np == max_paths) break;
+      if (d == 0) break;
+      --d; /* back up one step and try the next mask there */
+      for (int i = 0; i < k; ++i)
+        if ((path[d] >> i) & 1) lin += stride[i];
+    }
+    /* coordinates of the current cell */
+    int64_t rem = lin;
+    for (int i = 0; i < k; ++i) {
+      v[i] = rem / stride[i];
+      rem -= v[i] * stride[i];
+    }
+    /* the next mask above path[d] whose step can still end at or above the
+     * threshold */
+    int taken = 0;
+    for (int b = path[d] + 1; b < nmask && !taken; ++b) {
+      int ok = 1;
+      int64_t pred = lin;
+      for (int i = 0; i < k; ++i) {
+        if ((b >> i) & 1) {
+          if (v[i] == 0) { ok = 0; break; }
+          pred -= stride[i];
+        }
+      }
+      if (!ok) continue;
+      build_column(k, v, b, seqs, col);
+      const int64_t s = sp_score(k, col, alpha, sub, gap);
+      if (xi[pred] + s + sfx[d] >= threshold) {
+        path[d] = b;
+        sfx[d + 1] = sfx[d] + s;
+        lin = pred;
+        ++d;
+        path[d] = 0;
+        taken = 1;
+      }
+    }
+    if (taken) continue;
+    /* no mask left here: back up */
+    if (d == 0) break;
+    --d;
+    for (int i = 0; i < k; ++i)
+      if ((path[d] >> i) & 1) lin += stride[i];
+  }
+  *score_out = xi[ncell - 1];
+  *npaths_out = np;
+  free(xi);
+  free(D);
+  free(path);
+  free(sfx);
+  return 0;
+}

@@ -108,6 +108,32 @@ int msa_oracle_coopt(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
                      int64_t aln_cap, int64_t *aln_len_out, int32_t *npaths_out);
 
 /*
+ * Near-optimal alignments (Section 6: the alignments whose score lies within
+ * a threshold set by the user of the optimum): every global alignment with
+ * sum-of-pairs score >= opt - delta.  xi(u), the optimal score of a path from
+ * the origin to u, is reached by some path; so a walk from the far corner that
+ * has collected the suffix score s on reaching cell v can still end at or
+ * above the threshold through mask b exactly when
+ *     xi(v - b) + SP(col(v, b)) + s >= opt - delta.
+ * Walking only such steps enumerates exactly the near-optimal alignments,
+ * with no dead end.  Depth first, the masks of each cell tried in ascending
+ * order, as msa_oracle_coopt: alignments come in lexicographic order of their
+ * column masks read from the last column to the first, and with delta = 0 the
+ * list is msa_oracle_coopt's.
+ *   delta       : >= 0
+ *   max_paths   : at most this many alignments are returned (>= 1)
+ *   score_out   : the optimal score
+ *   scores_out  : max_paths int64, the score of each alignment returned
+ *   aln_out, aln_len_out, npaths_out : as msa_oracle_coopt
+ * Any k in 2..8.  Returns 0, or -1 on invalid input / allocation failure.
+ */
+int msa_oracle_nearopt(int32_t k, const int32_t *lens, const uint8_t *const *seqs,
+                       int32_t alpha, const int32_t *sub, int32_t gap, int64_t delta,
+                       int32_t max_paths, int64_t *score_out, int64_t *scores_out,
+                       uint8_t *aln_out, int64_t aln_cap, int64_t *aln_len_out,
+                       int32_t *npaths_out);
+
+/*
  * Score every cell: writes the full int64 score tensor (prod(lens[i]+1)
  * entries, same layout as dir_out) without a traceback.  Returns 0 or -1.
  */

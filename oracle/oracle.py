@@ -65,6 +65,13 @@ def _load():
         ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32,
         ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
+    lib.msa_oracle_nearopt.restype = ctypes.c_int
+    lib.msa_oracle_nearopt.argtypes = [
+        ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+        ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+        ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+        ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
     lib.msa_oracle_fill.restype = ctypes.c_int
     lib.msa_oracle_fill.argtypes = [
         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -167,6 +174,31 @@ def oracle_coopt(seqs, sub, gap: int, max_paths: int, want_ties: bool = False):
         raise ValueError("oracle rejected the input")
     rows = [aln[p, :, : alen[p]].copy() for p in range(npaths.value)]
     return int(score.value), rows, ties
+
+
+def oracle_nearopt(seqs, sub, gap: int, delta: int, max_paths: int):
+    """Up to ``max_paths`` alignments scoring at least opt - ``delta`` (see
+    ``msa_oracle_nearopt``).
+
+    Returns ``(opt, [(score, rows), ...])``; fewer than ``max_paths``
+    alignments means all of them."""
+    lib = _load()
+    seqs, k, lens, ptrs, sub, alpha = _marshal(seqs, sub)
+    total = int(sum(len(s) for s in seqs))
+    cap = max(total, 1)
+    aln = np.full((max_paths, k, cap), GAP, dtype=np.uint8)
+    alen = np.zeros(max_paths, dtype=np.int64)
+    scores = np.zeros(max_paths, dtype=np.int64)
+    score = ctypes.c_int64(0)
+    npaths = ctypes.c_int32(0)
+    rc = lib.msa_oracle_nearopt(
+        k, lens, ptrs, alpha, sub.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        int(gap), int(delta), int(max_paths), ctypes.byref(score), scores.ctypes.data,
+        aln.ctypes.data, cap, alen.ctypes.data, ctypes.byref(npaths))
+    if rc != 0:
+        raise ValueError("oracle rejected the input")
+    out = [(int(scores[p]), aln[p, :, : alen[p]].copy()) for p in range(npaths.value)]
+    return int(score.value), out
 
 
 def oracle_fill(seqs, sub, gap: int):
