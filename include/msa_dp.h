@@ -61,6 +61,7 @@ enum {
 #define MSA_END_GAPS_FREE 1u /* end-gap-free alignment, see msa_dp_align_ex */
 #define MSA_COOPTIMAL 2u     /* tie sets kept for msa_dp_align_coopt */
 #define MSA_PRUNE 4u         /* exact tile pruning, see msa_dp_align_ex */
+#define MSA_NEAROPT 8u       /* cell scores kept for msa_dp_nearopt_dev */
 
 /* Human-readable text for a status code (static storage). */
 const char *msa_strerror(int status);
@@ -142,6 +143,52 @@ int msa_dp_align_coopt(const uint8_t *const *seqs, const int32_t *lens, int32_t 
                        int64_t *score_out, uint8_t *aln_out, int64_t aln_cap,
                        int64_t *aln_len_out, int32_t *npaths_out);
 
+/* ------------------------------------------------------------------------
+ * msa_dp_align_nearopt: up to max_paths near-optimal alignments, every global
+ * alignment whose sum-of-pairs score is at least opt - delta (Section 6: the
+ * alignments within a threshold of the optimum set by the user).  The fill
+ * also keeps every cell's score xi; a walk from the far corner then takes a
+ * step v -> v - b only when xi(v - b) + SP(col(v, b)) plus the score of the
+ * columns already taken reaches opt - delta, which some alignment through
+ * that step does, so the walk has no dead end.  Synchronous, host buffers,
+ * same device-memory cache as msa_dp_align.
+ *   delta       : >= 0
+ *   max_paths   : >= 1
+ *   score_out   : the optimal score
+ *   scores_out  : max_paths int64, the score of each alignment written
+ *   aln_out     : max_paths blocks of k rows of aln_cap bytes (as
+ *                 msa_dp_align_coopt)
+ *   aln_len_out : max_paths int64 column counts
+ *   npaths_out  : number of alignments written; fewer than max_paths means
+ *                 every alignment at or above the threshold was written
+ * Order: the masks of each cell are tried in ascending order, so the list is
+ * sorted by the column masks read from the last column to the first;
+ * delta = 0 gives msa_dp_align_coopt's list.  Requires k <= 6 and
+ * sum(lens) <= 4096; the workspace needs 4 more bytes per cell (padded like
+ * the direction blocks, msa_dp_workspace_bytes_ex).  Errors as msa_dp_align,
+ * and MSA_EINVAL for k > 6, delta < 0 or max_paths < 1, MSA_ERANGE for
+ * longer inputs.
+ * ---------------------------------------------------------------------- */
+int msa_dp_align_nearopt(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
+                         const int8_t *submat, int32_t alpha, int32_t gap, int64_t delta,
+                         int32_t max_paths, int64_t *score_out, int64_t *scores_out,
+                         uint8_t *aln_out, int64_t aln_cap, int64_t *aln_len_out,
+                         int32_t *npaths_out);
+
+/* Device-buffer form of msa_dp_align_nearopt on a workspace of at least
+ * msa_dp_workspace_bytes_ex(lens, k, MSA_NEAROPT) bytes prepared with
+ * msa_dp_prepare_ex(..., MSA_NEAROPT, ...): enqueues the fill and the walk on
+ * hip_stream (asynchronous).  d_scores holds max_paths int64, the other
+ * outputs as msa_dp_coopt_dev; d_status MSA_EINVAL when the workspace was not
+ * prepared with MSA_NEAROPT (d_npaths and d_score then read 0).  Returns
+ * MSA_EINVAL / MSA_ERANGE at once, enqueuing nothing, for the argument errors
+ * of msa_dp_align_nearopt or those of msa_dp_align_dev. */
+int msa_dp_nearopt_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
+                       const int32_t *lens, int32_t k, int64_t delta, int32_t max_paths,
+                       int64_t *d_score, int64_t *d_scores, uint8_t *d_aln, int64_t aln_cap,
+                       int64_t *d_aln_len, int32_t *d_npaths, int32_t *d_status,
+                       void *hip_stream);
+
 /* Device-buffer form of msa_dp_align_coopt on a workspace prepared with
  * msa_dp_prepare_ex(..., MSA_COOPTIMAL, ...): enqueues the fill and the
  * enumeration on hip_stream (asynchronous).  d_aln holds max_paths * k rows
@@ -184,6 +231,13 @@ int msa_dp_coopt_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
  *   enqueued.  Calls on one workspace must be stream-ordered.
  * ---------------------------------------------------------------------- */
 int64_t msa_dp_workspace_bytes(const int32_t *lens, int32_t k);
+
+/* msa_dp_workspace_bytes for a workspace to be prepared with mode `flags`
+ * (msa_dp_prepare_ex): MSA_NEAROPT adds one int32 cell score per cell
+ * (padded like the direction blocks); the other modes need no more than
+ * msa_dp_workspace_bytes.  Same returns, and MSA_EINVAL / MSA_ERANGE for
+ * flags the shape does not allow. */
+int64_t msa_dp_workspace_bytes_ex(const int32_t *lens, int32_t k, uint32_t flags);
 
 int msa_dp_prepare(void *d_workspace, int64_t ws_bytes, const int32_t *lens,
                    int32_t k, const int8_t *submat, int32_t alpha,

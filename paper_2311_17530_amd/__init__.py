@@ -16,6 +16,7 @@ from ._lib import (  # noqa: F401
     MSA_ERANGE,
     MSA_ESHUTDOWN,
     MSA_OK,
+    MSA_NEAROPT,
     MSA_PRUNE,
     DeviceAligner,
     MsaError,
@@ -23,6 +24,7 @@ from ._lib import (  # noqa: F401
     align,
     align_batch,
     align_coopt,
+    align_nearopt,
     exported_names,
     lib,
     check_scoring,
@@ -32,4 +34,5 @@ from ._lib import (  # noqa: F401
     tile_grid,
     wave_counts,
     workspace_bytes,
+    workspace_bytes_ex,
 )

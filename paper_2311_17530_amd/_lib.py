@@ -59,6 +59,7 @@ class MsaResult(ctypes.Structure):
 MSA_END_GAPS_FREE = 1
 MSA_COOPTIMAL = 2
 MSA_PRUNE = 4
+MSA_NEAROPT = 8
 
 _SIGS = {
     "msa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -71,7 +72,12 @@ _SIGS = {
     "msa_dp_align_coopt": (ctypes.c_int, [ctypes.POINTER(c_vp), c_i32p, ctypes.c_int32, c_vp,
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                           c_i64p, c_vp, ctypes.c_int64, c_vp, c_i32p]),
+    "msa_dp_align_nearopt": (ctypes.c_int, [ctypes.POINTER(c_vp), c_i32p, ctypes.c_int32, c_vp,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                            ctypes.c_int32, c_i64p, c_vp, c_vp, ctypes.c_int64,
+                                            c_vp, c_i32p]),
     "msa_dp_workspace_bytes": (ctypes.c_int64, [c_i32p, ctypes.c_int32]),
+    "msa_dp_workspace_bytes_ex": (ctypes.c_int64, [c_i32p, ctypes.c_int32, ctypes.c_uint32]),
     "msa_dp_prepare": (ctypes.c_int, [c_vp, ctypes.c_int64, c_i32p, ctypes.c_int32, c_vp,
                                       ctypes.c_int32, ctypes.c_int32, c_vp]),
     "msa_dp_prepare_ex": (ctypes.c_int, [c_vp, ctypes.c_int64, c_i32p, ctypes.c_int32, c_vp,
@@ -93,6 +99,9 @@ _SIGS = {
     "msa_dp_coopt_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p, ctypes.c_int32,
                                         ctypes.c_int32, c_vp, c_vp, ctypes.c_int64, c_vp,
                                         c_vp, c_vp, c_vp]),
+    "msa_dp_nearopt_dev": (ctypes.c_int, [c_vp, ctypes.c_int64, c_vp, c_i32p, ctypes.c_int32,
+                                          ctypes.c_int64, ctypes.c_int32, c_vp, c_vp, c_vp,
+                                          ctypes.c_int64, c_vp, c_vp, c_vp, c_vp]),
     "msa_dp_align_batch": (ctypes.c_int, [ctypes.POINTER(MsaJob), ctypes.c_int32,
                                           ctypes.POINTER(MsaResult), ctypes.c_int64]),
     "msa_server_create": (c_vp, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
@@ -249,6 +258,38 @@ def align_coopt(seqs, sub, gap, max_paths: int):
     return int(score.value), [out[p, :, : lens_out[p]].copy() for p in range(npaths.value)]
 
 
+def align_nearopt(seqs, sub, gap, delta: int, max_paths: int):
+    """Up to ``max_paths`` alignments scoring at least opt - ``delta`` through
+    ``msa_dp_align_nearopt``.
+
+    Returns ``(opt, [(score, rows), ...])``; fewer than ``max_paths``
+    alignments means all of them."""
+    seqs = [np.ascontiguousarray(np.asarray(s, dtype=np.uint8)) for s in seqs]
+    sub = np.ascontiguousarray(np.asarray(sub, dtype=np.int8))
+    k = len(seqs)
+    cap = max(1, sum(len(s) for s in seqs))
+    out = np.full((int(max_paths), k, cap), GAP, dtype=np.uint8)
+    lens_out = np.zeros(max(1, int(max_paths)), dtype=np.int64)
+    scores = np.zeros(max(1, int(max_paths)), dtype=np.int64)
+    ptrs = (c_vp * k)(*[s.ctypes.data if len(s) else None for s in seqs])
+    score, npaths = ctypes.c_int64(), ctypes.c_int32()
+    rc = lib().msa_dp_align_nearopt(ptrs, _i32arr([len(s) for s in seqs]), k, sub.ctypes.data,
+                                    sub.shape[0], int(gap), int(delta), int(max_paths),
+                                    ctypes.byref(score), scores.ctypes.data, out.ctypes.data,
+                                    cap, lens_out.ctypes.data, ctypes.byref(npaths))
+    _check(rc, "msa_dp_align_nearopt")
+    return int(score.value), [(int(scores[p]), out[p, :, : lens_out[p]].copy())
+                              for p in range(npaths.value)]
+
+
+def workspace_bytes_ex(lens, flags: int) -> int:
+    """``msa_dp_workspace_bytes_ex``: workspace bytes for a mode."""
+    n = lib().msa_dp_workspace_bytes_ex(_i32arr(lens), len(lens), int(flags))
+    if n < 0:
+        raise MsaError(int(n), "msa_dp_workspace_bytes_ex")
+    return int(n)
+
+
 # ---------------------------------------------------------------------------
 # plain path, device buffers (torch provides memory and the stream)
 # ---------------------------------------------------------------------------
@@ -259,7 +300,7 @@ class DeviceAligner:
     enqueues one alignment on the current torch stream (asynchronous)."""
 
     def __init__(self, lens, sub, gap, device="cuda", end_gaps_free: bool = False,
-                 cooptimal: bool = False, prune: bool = False):
+                 cooptimal: bool = False, prune: bool = False, nearopt: bool = False):
         import torch
         self.torch = torch
         self.lens = [int(x) for x in lens]
@@ -267,7 +308,10 @@ class DeviceAligner:
         self.device = torch.device(device)
         self.sub = np.ascontiguousarray(np.asarray(sub, dtype=np.int8))
         self.gap = int(gap)
-        self.ws_bytes = workspace_bytes(self.lens)
+        flags = ((MSA_END_GAPS_FREE if end_gaps_free else 0)
+                 | (MSA_COOPTIMAL if cooptimal else 0) | (MSA_PRUNE if prune else 0)
+                 | (MSA_NEAROPT if nearopt else 0))
+        self.ws_bytes = workspace_bytes_ex(self.lens, flags)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         self.ws_ptr = (base + 255) & ~255
@@ -277,8 +321,6 @@ class DeviceAligner:
         self.d_score = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.d_len = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.d_status = torch.zeros(1, dtype=torch.int32, device=self.device)
-        flags = ((MSA_END_GAPS_FREE if end_gaps_free else 0)
-                 | (MSA_COOPTIMAL if cooptimal else 0) | (MSA_PRUNE if prune else 0))
         rc = lib().msa_dp_prepare_ex(self.ws_ptr, self.ws_bytes, _i32arr(self.lens), self.k,
                                      self.sub.ctypes.data, self.sub.shape[0], self.gap,
                                      flags, self._stream())
@@ -342,6 +384,40 @@ class DeviceAligner:
         lens = self.d_co_len[:n].cpu().numpy()
         aln = self.d_co_aln[:n].cpu().numpy()
         return int(self.d_score.item()), [aln[p, :, : lens[p]].copy() for p in range(n)]
+
+    def run_nearopt(self, delta: int, max_paths: int):
+        """Enqueue the fill and the walk of up to ``max_paths`` alignments
+        scoring at least opt - ``delta`` (``msa_dp_nearopt_dev``); read them
+        with ``result_nearopt``."""
+        t = self.torch
+        if getattr(self, "_no_max", 0) != max_paths:
+            self._no_max = int(max_paths)
+            self.d_no_aln = t.full((self._no_max, self.k, self.cap), GAP, dtype=t.uint8,
+                                   device=self.device)
+            self.d_no_len = t.zeros(max(1, self._no_max), dtype=t.int64, device=self.device)
+            self.d_no_sc = t.zeros(max(1, self._no_max), dtype=t.int64, device=self.device)
+            self.d_no_np = t.zeros(1, dtype=t.int32, device=self.device)
+        rc = lib().msa_dp_nearopt_dev(self.ws_ptr, self.ws_bytes, self.d_seqs.data_ptr(),
+                                      _i32arr(self.lens), self.k, int(delta), int(max_paths),
+                                      self.d_score.data_ptr(), self.d_no_sc.data_ptr(),
+                                      self.d_no_aln.data_ptr(), self.cap,
+                                      self.d_no_len.data_ptr(), self.d_no_np.data_ptr(),
+                                      self.d_status.data_ptr(), self._stream())
+        _check(rc, "msa_dp_nearopt_dev")
+
+    def result_nearopt(self):
+        """Synchronise and return ``(opt, [(score, rows), ...])`` of
+        ``run_nearopt``."""
+        self.torch.cuda.current_stream(self.device).synchronize()
+        st = int(self.d_status.item())
+        if st != MSA_OK:
+            raise MsaError(st, "device status")
+        n = int(self.d_no_np.item())
+        lens = self.d_no_len[:n].cpu().numpy()
+        sc = self.d_no_sc[:n].cpu().numpy()
+        aln = self.d_no_aln[:n].cpu().numpy()
+        return int(self.d_score.item()), [(int(sc[p]), aln[p, :, : lens[p]].copy())
+                                          for p in range(n)]
 
     def result(self):
         """Synchronise and return ``(score, rows)`` (raises on device status)."""

@@ -92,7 +92,12 @@ extern "C" int64_t msa_dp_workspace_bytes(const int32_t *lens, int32_t k) {
 // The pruned mode needs 3 <= k <= 6 and lengths below kPruneMaxLen (its
 // pairwise bounds assume the global alignment's start and end).
 static int check_flags(const Plan &p, uint32_t flags) {
-  if (flags & ~(uint32_t)(MSA_END_GAPS_FREE | MSA_COOPTIMAL | MSA_PRUNE)) return MSA_EINVAL;
+  if (flags & ~(uint32_t)(MSA_END_GAPS_FREE | MSA_COOPTIMAL | MSA_PRUNE | MSA_NEAROPT))
+    return MSA_EINVAL;
+  if (flags & MSA_NEAROPT) {  // a mode of its own: the plain fill plus cell scores
+    if (flags != MSA_NEAROPT || p.k > kNoMaxK) return MSA_EINVAL;
+    if (p.total_len > kNoMaxTotal) return MSA_ERANGE;
+  }
   if ((flags & MSA_END_GAPS_FREE) && (flags & (MSA_COOPTIMAL | MSA_PRUNE))) return MSA_EINVAL;
   if (flags & MSA_PRUNE) {
     if (p.k < kPruneMinK || p.k > kPruneMaxK) return MSA_EINVAL;
@@ -104,6 +109,23 @@ static int check_flags(const Plan &p, uint32_t flags) {
     if (p.total_len > kCoMaxTotal) return MSA_ERANGE;
   }
   return MSA_OK;
+}
+
+// Workspace bytes for a mode: the near-optimal mode's cell scores follow
+// the plain layout.
+static int64_t ws_need(const Plan &p, uint32_t flags) {
+  return p.bytes + ((flags & MSA_NEAROPT) ? nearopt_bytes(p) : 0);
+}
+
+extern "C" int64_t msa_dp_workspace_bytes_ex(const int32_t *lens, int32_t k, uint32_t flags) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  rc = check_flags(p, flags);
+  if (rc) return rc;
+  return ws_need(p, flags);
 }
 
 extern "C" int msa_dp_check_scoring(const int32_t *lens, int32_t k, const int8_t *submat,
@@ -131,7 +153,7 @@ extern "C" int msa_dp_prepare_ex(void *d_workspace, int64_t ws_bytes, const int3
   if (rc) return rc;
   rc = check_scoring_mode(lens, k, submat, alpha, gap, flags);
   if (rc) return rc;
-  if (ws_bytes < p.bytes) return MSA_EINVAL;
+  if (ws_bytes < ws_need(p, flags)) return MSA_EINVAL;
   return prepare_workspace(p, (char *)d_workspace, submat, alpha, gap, (int32_t)flags,
                            (hipStream_t)hip_stream);
 }
@@ -238,6 +260,28 @@ extern "C" int msa_dp_coopt_dev(void *d_workspace, int64_t ws_bytes, const uint8
                    d_aln_len, d_npaths, d_status, (hipStream_t)hip_stream);
 }
 
+extern "C" int msa_dp_nearopt_dev(void *d_workspace, int64_t ws_bytes, const uint8_t *d_seqs,
+                                  const int32_t *lens, int32_t k, int64_t delta,
+                                  int32_t max_paths, int64_t *d_score, int64_t *d_scores,
+                                  uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len,
+                                  int32_t *d_npaths, int32_t *d_status, void *hip_stream) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255) || !d_score || !d_scores || !d_aln_len ||
+      !d_npaths || !d_status || !d_aln || max_paths < 1 || delta < 0)
+    return MSA_EINVAL;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  rc = check_flags(p, MSA_NEAROPT);
+  if (rc) return rc;
+  if (ws_bytes < ws_need(p, MSA_NEAROPT) || aln_cap < p.total_len ||
+      (p.total_len > 0 && !d_seqs))
+    return MSA_EINVAL;
+  return run_nearopt(p, (char *)d_workspace, d_seqs, delta, max_paths, d_score, d_scores, d_aln,
+                     aln_cap, d_aln_len, d_npaths, d_status, (hipStream_t)hip_stream);
+}
+
 // ---------------------------------------------------------------------------
 // Host-buffer convenience path: a per-thread cache of device buffers.
 // ---------------------------------------------------------------------------
@@ -266,6 +310,7 @@ thread_local HostCache g_cache;
 static int host_call_setup(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
                            const int8_t *submat, int32_t alpha, int32_t gap, uint32_t flags,
                            const Plan &p, int64_t io_need) {
+  const int64_t wsb = ws_need(p, flags);
   for (int i = 0; i < k; ++i)
     if (lens[i] > 0 && !seqs[i]) return MSA_EINVAL;
   for (int i = 0; i < k; ++i)
@@ -283,16 +328,16 @@ static int host_call_setup(const uint8_t *const *seqs, const int32_t *lens, int3
     if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess)
       return MSA_EDEVICE;
   }
-  if (c.ws_bytes < p.bytes) {
+  if (c.ws_bytes < wsb) {
     if (c.ws) (void)hipFree(c.ws);
     c.ws = nullptr;
     c.ws_bytes = 0;
     c.k = 0;
-    if (hipMalloc(&c.ws, p.bytes) != hipSuccess) {
+    if (hipMalloc(&c.ws, wsb) != hipSuccess) {
       c.ws = nullptr;
       return MSA_ENOMEM;
     }
-    c.ws_bytes = p.bytes;
+    c.ws_bytes = wsb;
   }
   if (c.io_bytes < io_need) {
     if (c.io) (void)hipFree(c.io);
@@ -423,6 +468,62 @@ extern "C" int msa_dp_align_coopt(const uint8_t *const *seqs, const int32_t *len
   const int32_t np = (int32_t)(misc[1] & 0xffffffff);
   if (np < 1 || np > max_paths) return MSA_EDEVICE;
   if (hipMemcpyAsync(aln_len_out, d_len, (size_t)np * 8, hipMemcpyDeviceToHost, c.stream) !=
+          hipSuccess ||
+      (blk > 0 && hipMemcpyAsync(aln_out, d_aln, (size_t)(np * blk), hipMemcpyDeviceToHost,
+                                 c.stream) != hipSuccess))
+    return MSA_EDEVICE;
+  if (hipStreamSynchronize(c.stream) != hipSuccess) return MSA_EDEVICE;
+  *score_out = misc[0];
+  *npaths_out = np;
+  return MSA_OK;
+}
+
+extern "C" int msa_dp_align_nearopt(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
+                                    const int8_t *submat, int32_t alpha, int32_t gap,
+                                    int64_t delta, int32_t max_paths, int64_t *score_out,
+                                    int64_t *scores_out, uint8_t *aln_out, int64_t aln_cap,
+                                    int64_t *aln_len_out, int32_t *npaths_out) {
+  int rc = validate_shape(lens, k);
+  if (rc) return rc;
+  if (!seqs || !score_out || !scores_out || !aln_len_out || !npaths_out || !aln_out ||
+      max_paths < 1 || delta < 0)
+    return MSA_EINVAL;
+  Plan p;
+  rc = make_plan(lens, k, &p);
+  if (rc) return rc;
+  rc = check_flags(p, MSA_NEAROPT);
+  if (rc) return rc;
+  if (aln_cap < p.total_len) return MSA_EINVAL;
+  // device I/O: seqs | max_paths blocks of k rows | lengths | scores | score, npaths, status
+  const int64_t seq_b = (p.total_len + 255) & ~255LL;
+  const int64_t blk = (int64_t)k * aln_cap;
+  if (blk > 0 && max_paths > (INT64_MAX / 4) / blk) return MSA_ENOMEM;
+  const int64_t aln_b = ((int64_t)max_paths * blk + 255) & ~255LL;
+  const int64_t len_b = ((int64_t)max_paths * 8 + 255) & ~255LL;
+  const int64_t io_need = seq_b + aln_b + 2 * len_b + 256;
+  rc = host_call_setup(seqs, lens, k, submat, alpha, gap, MSA_NEAROPT, p, io_need);
+  if (rc) return rc;
+  HostCache &c = g_cache;
+  uint8_t *d_seqs = c.io;
+  uint8_t *d_aln = d_seqs + seq_b;
+  int64_t *d_len = (int64_t *)(d_aln + aln_b);
+  int64_t *d_sc = (int64_t *)((char *)d_len + len_b);
+  int64_t *d_misc = (int64_t *)((char *)d_sc + len_b);  // score | npaths | status
+  rc = run_nearopt(p, (char *)c.ws, d_seqs, delta, max_paths, d_misc, d_sc, d_aln, aln_cap,
+                   d_len, (int32_t *)(d_misc + 1), (int32_t *)(d_misc + 2), c.stream);
+  if (rc) return rc;
+  int64_t misc[3] = {0, 0, 0};
+  if (hipMemcpyAsync(misc, d_misc, sizeof(misc), hipMemcpyDeviceToHost, c.stream) !=
+      hipSuccess)
+    return MSA_EDEVICE;
+  if (hipStreamSynchronize(c.stream) != hipSuccess) return MSA_EDEVICE;
+  const int32_t st = (int32_t)(misc[2] & 0xffffffff);
+  if (st != MSA_OK) return st;
+  const int32_t np = (int32_t)(misc[1] & 0xffffffff);
+  if (np < 1 || np > max_paths) return MSA_EDEVICE;
+  if (hipMemcpyAsync(aln_len_out, d_len, (size_t)np * 8, hipMemcpyDeviceToHost, c.stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(scores_out, d_sc, (size_t)np * 8, hipMemcpyDeviceToHost, c.stream) !=
           hipSuccess ||
       (blk > 0 && hipMemcpyAsync(aln_out, d_aln, (size_t)(np * blk), hipMemcpyDeviceToHost,
                                  c.stream) != hipSuccess))

@@ -51,6 +51,7 @@ struct JobDev {
   const int32_t *corder;      // column schedule: first tile of each column, in order
   int32_t ncols;              // columns along dimension 0 (0: tile queue instead)
   int64_t *trace;             // optional per-tile phase timestamps (debug builds)
+  int32_t *scores;            // near-optimal mode: every cell's score, laid out as `dir`
   // batched path only
   int32_t *jstatus;           // per-job status (bad residue code)
   const int32_t *wcnt;        // (k+1) x nwaves: tuples (c_d..c_{k-1}) summing to s
@@ -114,6 +115,14 @@ struct PruneDev {
   const int64_t *score;        // the fill's end score
 };
 constexpr int kSelBlock = 1024;
+
+// Near-optimal mode (alignments within a threshold of the optimum): one wave
+// tests the 2^k - 1 masks of a cell at once (k <= 6), and the walk keeps its
+// stack (mask, masks passing the threshold and score so far per column, at
+// most sum n_i) in LDS.
+constexpr int32_t kNearOpt = 8;
+constexpr int kNoMaxK = 6;
+constexpr int kNoMaxTotal = 4096;
 
 // Co-optimal mode: tie sets fit a byte for k <= 3, and the enumeration keeps
 // its stack of masks (one per column, at most sum n_i) in LDS.

@@ -237,12 +237,15 @@ struct HaloSlots {
 // copied inside LDS instead of loaded, and its flag is not polled.
 // cols: column schedule; no tile reads a dimension-0 face plane, so none is
 // exported.
+// scores: near-optimal mode: every cell's score is stored as well, in the
+// layout of the direction block (jd.scores + tile * DBS).
 template <int K, int NT>
 __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int epoch,
                              Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm,
                              const HaloSlots<K, NT> &hs, bool egf = false,
                              int64_t *best_key = nullptr, bool coopt = false,
-                             bool prune = false, bool own0 = false, bool cols = false) {
+                             bool prune = false, bool own0 = false, bool cols = false,
+                             bool scores = false) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int E = C::E;
@@ -812,6 +815,24 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     }
   }
 
+  // ---- near-optimal mode: cell scores, index sum_i q_i * T^(k-1-i) ----
+  if (scores) {
+    int32_t *dst = jd.scores + (int64_t)tile * C::DBS;
+    constexpr int NC = ipow(T, K);
+    for (int idx = tid; idx < NC; idx += NT) {
+      int rem = idx, x = 0;
+      bool ok = true;
+#pragma unroll
+      for (int i = K - 1; i >= 0; --i) {
+        const int q = rem % T;
+        rem /= T;
+        ok = ok && q < ext[i];
+        x += (q + 1) * C::sstride(i);
+      }
+      if (ok) dst[idx] = sm.S[x] >> K;
+    }
+  }
+
 #ifdef MSA_TRACE
   if (jd.trace) jd.trace[(int64_t)tile * 8 + 7] = blockIdx.x;
 #endif
@@ -831,6 +852,7 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
   const bool egf = (mode & kEndGapsFree) != 0;
   const bool coopt = (mode & kCoOptimal) != 0;
   const bool prune = (mode & kPrune) != 0;
+  const bool nearopt = (mode & kNearOpt) != 0;
   // column schedule (not in pruned mode): a workgroup takes a column of tiles
   // along dimension 0 and computes it bottom up
   const bool cols = !prune && jd.ncols > 0;
@@ -860,11 +882,11 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
       for (int c0 = 0; c0 < jd.P[0]; ++c0)
         process_tile<K, NT>(jd, alpha, gap, base + c0 * jd.tstride[0], epoch, ctrl,
                                   &ctrl->status, sm, hs, egf, &ctrl->best, coopt, false,
-                                  c0 > 0, true);
+                                  c0 > 0, true, nearopt);
     } else {
       process_tile<K, NT>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]),
                                 epoch, ctrl, &ctrl->status, sm, hs, egf, &ctrl->best, coopt,
-                                prune);
+                                prune, false, false, nearopt);
     }
   }
 }
@@ -1278,6 +1300,246 @@ static int launch_coopt_k(const JobDev &jd, Ctrl *ctrl, int32_t max_paths, uint8
   }
 }
 
+// ---------------------------------------------------------------------------
+// Near-optimal alignments (near-optimal mode, k <= 6): every global alignment
+// whose score is at least opt - delta (Section 6: alignments within a
+// threshold of the optimum set by the user).  The fill has also stored every
+// cell's score xi, laid out as the direction blocks.  One wave walks depth
+// first from the far corner.  At cell v, with s the score of the columns
+// taken so far, lane b - 1 tests mask b: v - b lies in the tensor and
+// xi(v - b) + SP(col(v, b)) + s >= opt - delta.  xi(v - b) is the score of
+// some path from the origin, so every step passing the test leads to at least
+// one alignment at or above the threshold (the walk has no dead end), and
+// every such alignment is walked.  The masks of a cell are taken in
+// ascending order, so the list is sorted by the column masks read from the
+// last column to the first, and delta = 0 gives the co-optimal list.  Per
+// column the LDS stack keeps the mask taken, the set of masks that passed
+// and the score so far (sum n_i <= kNoMaxTotal); after an alignment the walk
+// jumps back to the deepest column with a passing mask left, found with one
+// wave-wide scan of the stack.  Alignment p goes to aln_out + p * k *
+// aln_cap, its score to scores_out[p].
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(64) void nearopt_kernel(JobDev jd, Ctrl *ctrl, int64_t delta,
+                                                     int32_t max_paths, int64_t *scores_out,
+                                                     uint8_t *aln_out, int64_t *len_out,
+                                                     int32_t *npaths_out) {
+  using C = Cfg<K>;
+  constexpr int T = C::T;
+  constexpr int M = (1 << K) - 1;  // masks 1..M; lane b - 1 tests mask b
+  static_assert(M <= 64, "one lane per mask");
+  __shared__ uint64_t pass_set[kNoMaxTotal + 1];
+  __shared__ int32_t sofar[kNoMaxTotal + 1];
+  __shared__ uint8_t path[kNoMaxTotal + 1];
+  const int tid = threadIdx.x;
+  int status = __builtin_amdgcn_readfirstlane(
+      __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  // the cell scores exist only when the workspace was set up for them
+  if (status == ST_OK && !(ctrl->flags & kNearOpt)) status = ST_EINVAL;
+  const int alpha = ctrl->alpha;
+  const int gap = ctrl->gap;
+  const int64_t threshold = *jd.score_out - delta;
+  const int bl = tid + 1;  // this lane's mask
+  // this lane's pair (pi, pj) for the pair scores of a cell (lane p < C(k,2))
+  int pi = 0, pj = 0, so = 0;
+  {
+    int p = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+      for (int j = i + 1; j < K; ++j) {
+        if (p == tid) {
+          pi = i;
+          pj = j;
+        }
+        ++p;
+      }
+#pragma unroll
+    for (int i = 0; i < K; ++i) so = tid == i ? jd.seq_off[i] : so;
+  }
+  int v[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = jd.n[i];
+  int d = 0, np = 0;
+  int tried = 0;      // masks up to this one were taken at depth d
+  bool fresh = true;  // pass_set[d] not computed yet
+  int64_t steps = 0;
+  const int64_t step_limit = (int64_t)max_paths * (2 * jd.total_len + 2) + 2;
+  sofar[0] = 0;  // every lane stores the same value
+  while (status == ST_OK) {
+    bool origin = true;
+#pragma unroll
+    for (int i = 0; i < K; ++i) origin = origin && v[i] == 0;
+    if (origin) {
+      // emit path[0..d) (path[d-1] is the first column) as alignment np
+      uint8_t *blk = aln_out + (int64_t)np * K * jd.aln_cap;
+      int cnt[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) cnt[i] = 0;
+      for (int c0 = 0; c0 < d; c0 += 64) {
+        const int col = c0 + tid;
+        const int m = col < d ? path[d - 1 - col] : 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          const int bit = (m >> i) & 1;
+          int incl = bit;
+          for (int sh = 1; sh < 64; sh <<= 1) {
+            const int y = __shfl_up(incl, sh, 64);
+            if (tid >= sh) incl += y;
+          }
+          const int pos = cnt[i] + incl - bit;
+          if (col < d)
+            blk[(int64_t)i * jd.aln_cap + col] = bit ? jd.seqs[jd.seq_off[i] + pos] : (uint8_t)0xFF;
+          cnt[i] += __shfl(incl, 63, 64);
+        }
+      }
+      if (tid == 0) {
+        len_out[np] = d;
+        scores_out[np] = sofar[d];
+      }
+      ++np;
+      if (np == max_paths || d == 0) break;
+      // back up to the deepest column with a passing mask above the one
+      // taken: scan the stack 64 entries at a time (lane x reads level
+      // e - x), adding the masks of the levels popped to v
+      int e = d - 1, found = -1;
+      int back[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) back[i] = 0;
+      while (e >= 0) {
+        const int lvl = e - tid;
+        const int ent = lvl >= 0 ? path[lvl] : 0;
+        const bool more = lvl >= 0 && (pass_set[lvl] >> ent) != 0;
+        const uint64_t flagged = __ballot(more);
+        const int upto = flagged ? __builtin_ctzll(flagged) : 63;
+        const bool popped = tid <= upto && lvl >= 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+          back[i] += __builtin_popcountll(__ballot(popped && ((ent >> i) & 1)));
+        if (flagged) {
+          found = e - upto;
+          break;
+        }
+        e -= 64;
+      }
+      if (found < 0) break;  // every alignment has been produced
+#pragma unroll
+      for (int i = 0; i < K; ++i) v[i] += back[i];
+      d = found;
+      tried = path[d];
+      fresh = false;
+      continue;
+    }
+    if (++steps > step_limit) {  // inconsistent scores: never loop for ever
+      status = ST_EDEVICE;
+      break;
+    }
+    // residues of cell v (lane i < k loads r_i) and its pair scores (lane p)
+    int vi = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) vi = tid == i ? v[i] : vi;
+    int rown = 0;
+    if (tid < K && vi >= 1) rown = jd.seqs[so + vi - 1];
+    int r[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) r[i] = __shfl(rown, i, 64);
+    int ri = 0, rj = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      ri = pi == i ? r[i] : ri;
+      rj = pj == i ? r[i] : rj;
+    }
+    const int pown = tid < K * (K - 1) / 2 ? (int)jd.sub[ri * alpha + rj] : 0;
+    // SP(col(v, b)) of this lane's mask: residue pairs, residue-gap pairs
+    int32_t sp = 0;
+    {
+      int p = 0;
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = i + 1; j < K; ++j) {
+          const int bi = (bl >> i) & 1, bj = (bl >> j) & 1;
+          const int32_t ps = __shfl(pown, p, 64);
+          sp += (bi && bj) ? ps : (bi ^ bj) ? gap : 0;
+          ++p;
+        }
+    }
+    if (fresh) {
+      // xi(v - b) of this lane's mask, in the layout of the direction blocks
+      bool ok = tid < M;
+      int t = 0, dl = 0;
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int u = v[i] - ((bl >> i) & 1);
+        ok = ok && u >= 0;
+        const int uu = u < 0 ? 0 : u;
+        const int ci = uu == 0 ? 0 : (uu - 1) / T + 1;
+        t += ci * jd.tstride[i];
+        dl += (uu - (ci == 0 ? 0 : (ci - 1) * T + 1)) * C::dstride(i);
+      }
+      const int32_t xi = ok ? jd.scores[(int64_t)t * C::DBS + dl] : 0;
+      const bool pass = ok && (int64_t)xi + sp + sofar[d] >= threshold;
+      const uint64_t set = __ballot(pass);
+      if (set == 0) {  // a cell off the origin from which no alignment reaches the threshold
+        status = ST_EDEVICE;
+        break;
+      }
+      pass_set[d] = set;  // every lane stores the same value
+      fresh = false;
+    }
+    const uint64_t set = pass_set[d];
+    const uint64_t rest = set & ~((1ull << tried) - 1);  // masks above `tried`
+    if (rest != 0) {
+      const int b = __builtin_ctzll(rest) + 1;
+      if (d >= jd.total_len) {  // a walk longer than any alignment
+        status = ST_EDEVICE;
+        break;
+      }
+      const int32_t spb = __shfl(sp, b - 1, 64);
+      // every lane stores the same values; the one wave's LDS accesses stay
+      // in program order, so no barrier is needed before they are read back
+      path[d] = (uint8_t)b;
+      sofar[d + 1] = sofar[d] + spb;
+#pragma unroll
+      for (int i = 0; i < K; ++i) v[i] -= (b >> i) & 1;
+      ++d;
+      tried = 0;
+      fresh = true;
+      continue;
+    }
+    if (d == 0) break;  // every alignment has been produced
+    --d;
+    tried = path[d];
+#pragma unroll
+    for (int i = 0; i < K; ++i) v[i] += (tried >> i) & 1;
+    fresh = false;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    *npaths_out = status == ST_OK ? np : 0;
+    *jd.status_out = status;
+    if (status != ST_OK) *jd.score_out = 0;
+    // ready the control block for the next launch on this workspace
+    ctrl->head = 0;
+    ctrl->status = ST_OK;
+    ctrl->best = INT64_MIN;
+    ctrl->epoch = ctrl->epoch + 1;
+  }
+}
+
+template <int K>
+static int launch_nearopt_k(const JobDev &jd, Ctrl *ctrl, int64_t delta, int32_t max_paths,
+                            int64_t *scores_out, uint8_t *aln_out, int64_t *len_out,
+                            int32_t *npaths_out, hipStream_t s) {
+  if constexpr (K <= kNoMaxK) {
+    hipLaunchKernelGGL((nearopt_kernel<K>), dim3(1), dim3(64), 0, s, jd, ctrl, delta, max_paths,
+                       scores_out, aln_out, len_out, npaths_out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  } else {
+    return -1;
+  }
+}
+
 // Row-major decision tensor (mask b per cell) from the tile-major blocks.
 template <int K>
 // A co-optimal workspace exports the bytes as stored (the tie sets) instead
@@ -1526,6 +1788,13 @@ int fill_occupancy(int k) { MSA_DISPATCH_K(k, occupancy_k); }
 int launch_coopt(const JobDev &jd, Ctrl *ctrl, int32_t max_paths, uint8_t *aln_out,
                  int64_t *len_out, int32_t *npaths_out, hipStream_t s) {
   MSA_DISPATCH_K(jd.k, launch_coopt_k, jd, ctrl, max_paths, aln_out, len_out, npaths_out, s);
+}
+
+int launch_nearopt(const JobDev &jd, Ctrl *ctrl, int64_t delta, int32_t max_paths,
+                   int64_t *scores_out, uint8_t *aln_out, int64_t *len_out, int32_t *npaths_out,
+                   hipStream_t s) {
+  MSA_DISPATCH_K(jd.k, launch_nearopt_k, jd, ctrl, delta, max_paths, scores_out, aln_out,
+                 len_out, npaths_out, s);
 }
 
 int launch_export(const JobDev &jd, const Ctrl *ctrl, uint8_t *out, int64_t ncell,

@@ -230,6 +230,8 @@ int check_scoring_mode(const int32_t *lens, int32_t k, const int8_t *submat, int
   return MSA_OK;
 }
 
+int64_t nearopt_bytes(const Plan &p) { return align256(p.ntiles * (int64_t)p.dbs * 4); }
+
 void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd) {
   memset(jd, 0, sizeof(*jd));
   jd->k = p.k;
@@ -258,6 +260,7 @@ void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd) {
   jd->corder = reinterpret_cast<const int32_t *>(ws + p.off_corder);
   jd->ncols = (int32_t)p.ncols;
   jd->path = reinterpret_cast<uint8_t *>(ws + p.off_path);
+  jd->scores = ws ? reinterpret_cast<int32_t *>(ws + p.bytes) : nullptr;
 }
 
 }  // namespace msa

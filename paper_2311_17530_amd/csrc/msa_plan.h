@@ -76,6 +76,11 @@ int score_bounds(const int32_t *lens, int32_t k, const int8_t *submat, int32_t a
 int check_scoring_mode(const int32_t *lens, int32_t k, const int8_t *submat, int32_t alpha,
                        int32_t gap, uint32_t flags);
 
+// Near-optimal mode: bytes of the cell-score region that follows the plan's
+// layout (at offset p.bytes), one int32 per cell laid out as the direction
+// blocks.
+int64_t nearopt_bytes(const Plan &p);
+
 // Device descriptor for a plan placed at workspace base `ws`.
 void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd);
 

@@ -217,6 +217,24 @@ int run_coopt(const Plan &p, char *ws, const uint8_t *d_seqs, int32_t max_paths,
   return MSA_OK;
 }
 
+int run_nearopt(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t delta, int32_t max_paths,
+                int64_t *d_score, int64_t *d_scores, uint8_t *d_aln, int64_t aln_cap,
+                int64_t *d_aln_len, int32_t *d_npaths, int32_t *d_status, hipStream_t s) {
+  int32_t alpha = 0;
+  if (check_workspace(p, ws, &alpha) != MSA_OK) return MSA_EINVAL;
+  JobDev jd;
+  fill_jobdev(p, ws, 0, 0, &jd);
+  jd.seqs = d_seqs;
+  jd.score_out = d_score;
+  jd.aln_cap = aln_cap;
+  jd.status_out = d_status;
+  Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
+  if (run_fill(p, ws, jd, s, alpha) != 0) return MSA_EDEVICE;
+  if (launch_nearopt(jd, ctrl, delta, max_paths, d_scores, d_aln, d_aln_len, d_npaths, s) != 0)
+    return MSA_EDEVICE;
+  return MSA_OK;
+}
+
 int export_dirs(const Plan &p, char *ws, uint8_t *out, hipStream_t s) {
   if (check_workspace(p, ws, nullptr) != MSA_OK) return MSA_EINVAL;
   JobDev jd;

@@ -14,6 +14,9 @@ int launch_fill(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid, in
 int launch_traceback(const JobDev &jd, Ctrl *ctrl, hipStream_t s);
 int launch_export(const JobDev &jd, const Ctrl *ctrl, uint8_t *out, int64_t ncell,
                   hipStream_t s);
+int launch_nearopt(const JobDev &jd, Ctrl *ctrl, int64_t delta, int32_t max_paths,
+                   int64_t *scores_out, uint8_t *aln_out, int64_t *len_out, int32_t *npaths_out,
+                   hipStream_t s);
 int launch_coopt(const JobDev &jd, Ctrl *ctrl, int32_t max_paths, uint8_t *aln_out,
                  int64_t *len_out, int32_t *npaths_out, hipStream_t s);
 int fill_occupancy(int k);
@@ -54,6 +57,12 @@ int export_prune(const Plan &p, char *ws, uint8_t *keep_out, int64_t *info_out,
                  hipStream_t s);
 // fill, then up to max_paths co-optimal alignments (workspace prepared with
 // the co-optimal flag)
+// Near-optimal mode: the fill (cell scores kept) and the walk of the
+// alignments scoring at least opt - delta.
+int run_nearopt(const Plan &p, char *ws, const uint8_t *d_seqs, int64_t delta, int32_t max_paths,
+                int64_t *d_score, int64_t *d_scores, uint8_t *d_aln, int64_t aln_cap,
+                int64_t *d_aln_len, int32_t *d_npaths, int32_t *d_status, hipStream_t s);
+
 int run_coopt(const Plan &p, char *ws, const uint8_t *d_seqs, int32_t max_paths, int64_t *d_score,
               uint8_t *d_aln, int64_t aln_cap, int64_t *d_aln_len, int32_t *d_npaths,
               int32_t *d_status, hipStream_t s);

@@ -269,3 +269,37 @@ def test_unprepared_or_mismatched_workspace_rejected_before_device():
     rc = lib.msa_dp_coopt_dev(fake, 1 << 30, dummy, lens, 3, 1, dummy, dummy, 64, dummy, dummy,
                               dummy, None)
     assert rc == msa.MSA_EINVAL
+
+
+def test_nearopt_limits_and_workspace_before_device():
+    # near-optimal mode: k <= 6, sum of lengths <= 4096, a mode of its own,
+    # delta >= 0, max_paths >= 1; its workspace adds one int32 per cell
+    # (padded like the direction blocks) after the plain layout
+    sub, gap = dna_scoring()
+    a = np.array([0, 1, 2], np.uint8)
+    for seqs, delta, mp, want in (([a] * 7, 0, 1, msa.MSA_EINVAL), ([a, a], -1, 1, msa.MSA_EINVAL),
+                                  ([a, a], 0, 0, msa.MSA_EINVAL),
+                                  ([np.zeros(2049, np.uint8)] * 2, 0, 1, msa.MSA_ERANGE)):
+        with pytest.raises(msa.MsaError) as e:
+            msa.align_nearopt(seqs, sub, gap, delta, mp)
+        assert e.value.status == want
+    for lens in ([40, 40, 40], [9, 17, 5, 3], [100, 100]):
+        k = len(lens)
+        T = msa.tile_edge(k)
+        P, _ = msa.tile_grid(lens, T)
+        dbs = (T ** k + 15) // 16 * 16
+        extra = (int(np.prod(P)) * dbs * 4 + 255) // 256 * 256
+        assert msa.workspace_bytes_ex(lens, msa.MSA_NEAROPT) == msa.workspace_bytes(lens) + extra
+        assert msa.workspace_bytes_ex(lens, 0) == msa.workspace_bytes(lens)
+    for flags in (msa.MSA_NEAROPT | msa.MSA_PRUNE, msa.MSA_NEAROPT | msa.MSA_COOPTIMAL, 16):
+        with pytest.raises(msa.MsaError) as e:
+            msa.workspace_bytes_ex([10, 10, 10], flags)
+        assert e.value.status == msa.MSA_EINVAL
+    import ctypes
+    sub8 = np.ascontiguousarray(sub.astype(np.int8))
+    lens = (ctypes.c_int32 * 3)(10, 10, 10)
+    plain = msa.workspace_bytes([10, 10, 10])
+    ws = 256  # any aligned address: a workspace too small for the mode is rejected first
+    rc = msa.lib().msa_dp_prepare_ex(ws, plain, lens, 3, sub8.ctypes.data, 4, gap,
+                                     msa.MSA_NEAROPT, None)
+    assert rc == msa.MSA_EINVAL
