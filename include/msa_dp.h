@@ -135,8 +135,10 @@ int msa_dp_align_ex(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
  * Order: the walk from the far corner tries the tied masks of each cell in
  * ascending order, so alignment 0 is msa_dp_align's and the list is sorted
  * by the column masks read from the last column to the first.
- * Requires k <= 3 and sum(lens) <= 32768.  Errors as msa_dp_align, and
- * MSA_EINVAL for k > 3 or max_paths < 1, MSA_ERANGE for longer inputs.
+ * k <= 3 keeps a tie set per cell (sum(lens) <= 32768); 4 <= k <= 6 runs
+ * the walk of msa_dp_align_nearopt with delta = 0, which lists the same
+ * alignments in the same order (sum(lens) <= 4096).  Errors as msa_dp_align,
+ * and MSA_EINVAL for k > 6 or max_paths < 1, MSA_ERANGE for longer inputs.
  * ---------------------------------------------------------------------- */
 int msa_dp_align_coopt(const uint8_t *const *seqs, const int32_t *lens, int32_t k,
                        const int8_t *submat, int32_t alpha, int32_t gap, int32_t max_paths,

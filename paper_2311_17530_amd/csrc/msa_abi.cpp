@@ -433,6 +433,14 @@ extern "C" int msa_dp_align_coopt(const uint8_t *const *seqs, const int32_t *len
                                   int64_t aln_cap, int64_t *aln_len_out, int32_t *npaths_out) {
   int rc = validate_shape(lens, k);
   if (rc) return rc;
+  if (k > kCoMaxK && k <= kNoMaxK) {
+    // tie sets need more than a byte: the near-optimal walk at delta = 0
+    // lists the same alignments in the same order
+    if (max_paths < 1) return MSA_EINVAL;
+    std::vector<int64_t> sc((size_t)max_paths);
+    return msa_dp_align_nearopt(seqs, lens, k, submat, alpha, gap, 0, max_paths, score_out,
+                                sc.data(), aln_out, aln_cap, aln_len_out, npaths_out);
+  }
   if (!seqs || !score_out || !aln_len_out || !npaths_out || !aln_out || max_paths < 1)
     return MSA_EINVAL;
   Plan p;

@@ -150,12 +150,16 @@ def test_mode_flags_rejected_before_device():
 
 
 def test_coopt_limits_rejected_before_device():
-    # tie sets fit a byte for k <= 3; the walk's mask stack holds 32768 columns
+    # tie sets fit a byte for k <= 3 (the walk's mask stack holds 32768
+    # columns); k = 4..6 use the near-optimal walk (4096 columns)
     sub, gap = dna_scoring()
     a = np.array([0, 1, 2], np.uint8)
     with pytest.raises(msa.MsaError) as e:
-        msa.align_coopt([a] * 4, sub, gap, 4)
+        msa.align_coopt([a] * 7, sub, gap, 4)  # k = 4..6 go through the near-optimal walk
     assert e.value.status == msa.MSA_EINVAL
+    with pytest.raises(msa.MsaError) as e:
+        msa.align_coopt([np.zeros(1100, np.uint8)] * 4, sub, gap, 4)
+    assert e.value.status == msa.MSA_ERANGE
     with pytest.raises(msa.MsaError) as e:
         msa.align_coopt([a, a], sub, gap, 0)
     assert e.value.status == msa.MSA_EINVAL

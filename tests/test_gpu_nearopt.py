@@ -122,3 +122,17 @@ def test_nearopt_host_path_and_unprepared_workspace():
 def test_nearopt_full_size_protein_k3():
     job = workload("prot_k3_512")
     check_nearopt(job.seqs, job.sub, job.gap, 20, 16)
+
+
+def test_coopt_k4_to_6_through_the_nearopt_walk():
+    # msa_dp_align_coopt for k = 4..6 lists the delta = 0 alignments
+    rng = np.random.Generator(np.random.PCG64(9500))
+    sub, gap = dna_scoring()
+    for lens in ([12, 10, 11, 9], [6, 7, 5, 6, 7], [4, 3, 4, 4, 3, 4]):
+        seqs = [rng.integers(0, 4, size=n).astype(np.uint8) for n in lens]
+        say("coopt via nearopt lens=%s" % lens)
+        opt0, want = oracle_nearopt(seqs, sub, gap, 0, 50)
+        s1, rows = msa.align_coopt(seqs, sub, gap, 50)
+        assert s1 == opt0 and len(rows) == len(want)
+        for r1, (s0, r0) in zip(rows, want):
+            assert s0 == opt0 and np.array_equal(r1, r0)
