@@ -138,6 +138,21 @@ constexpr int kSwLanes = 64;       // lanes (dimension-1 cells) per wave
 constexpr int kSwSeqMax = 16384;   // longest third sequence (kept in LDS)
 constexpr int kSwSubMax = 32;      // largest alphabet (matrix kept in LDS)
 
+// Parameters of one batched launch, written into the launch's arena with its
+// inputs.  The launch sequence then takes only fixed arguments (this
+// descriptor's address, the control block, fixed grids), so it is captured
+// once per arena in a graph and replayed for every batch.
+struct BatchArgs {
+  const JobDev *jobs;         // njobs descriptors
+  const int64_t *jcols;       // njobs + 1: tile columns before job i
+  int32_t *qjob, *qtile;      // the column queue: job index and first tile
+  int32_t *flags;             // per-tile completion flags of all jobs
+  int64_t tiles;              // tiles of all jobs
+  int64_t cols;               // columns of all jobs (queue length)
+  int32_t njobs;
+  int32_t pad;
+};
+
 // One entry of the batched tile queue: (job index, tile linear index).
 struct QItem {
   int32_t job;

@@ -1580,9 +1580,12 @@ __global__ void export_dirs_kernel(JobDev jd, const Ctrl *ctrl, uint8_t *out, in
 // rank among those columns in lexicographic order of (c_1..c_{k-1}).  Every
 // job's columns appear in the order of their first tile's wave, which makes
 // the queue a topological order of all dependencies.
-__global__ void batch_queue_kernel(const JobDev *__restrict__ jobs, int njobs,
-                                   const int64_t *__restrict__ jcols, int32_t *qjob,
-                                   int32_t *qtile) {
+__global__ void batch_queue_kernel(const BatchArgs *__restrict__ a) {
+  const JobDev *__restrict__ jobs = a->jobs;
+  const int njobs = a->njobs;
+  const int64_t *__restrict__ jcols = a->jcols;
+  int32_t *qjob = a->qjob;
+  int32_t *qtile = a->qtile;
   const int64_t total = jcols[njobs];
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
@@ -1648,11 +1651,13 @@ __device__ void batch_column(const JobDev &jd, int base, int epoch, Ctrl *ctrl, 
 }
 
 template <int KLO, int KHI, int NT>
-__global__ __launch_bounds__(NT) void batch_fill_kernel(const JobDev *__restrict__ jobs,
-                                                        const int32_t *__restrict__ qjob,
-                                                        const int32_t *__restrict__ qtile,
-                                                        int32_t total, Ctrl *ctrl) {
+__global__ __launch_bounds__(NT) void batch_fill_kernel(const BatchArgs *__restrict__ a,
+                                                        Ctrl *ctrl) {
   __shared__ alignas(16) char smraw[batch_smem_bytes<KLO, KHI>()];
+  const JobDev *__restrict__ jobs = a->jobs;
+  const int32_t *__restrict__ qjob = a->qjob;
+  const int32_t *__restrict__ qtile = a->qtile;
+  const int32_t total = __builtin_amdgcn_readfirstlane((int32_t)a->cols);
   __shared__ int32_t bcast;
   const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) >> 6;
@@ -1683,32 +1688,37 @@ __global__ __launch_bounds__(NT) void batch_fill_kernel(const JobDev *__restrict
   }
 }
 
-// One workgroup (one wave) per job: walk, expand, write the outputs.
+// One workgroup (one wave) per job at a time (jobs blockIdx.x, + gridDim.x,
+// ...): walk, expand, write the outputs.
 template <int KLO, int KHI>
-__global__ __launch_bounds__(64) void batch_traceback_kernel(const JobDev *__restrict__ jobs,
-                                                             int njobs, Ctrl *ctrl) {
+__global__ __launch_bounds__(64) void batch_traceback_kernel(const BatchArgs *__restrict__ a,
+                                                             Ctrl *ctrl) {
   __shared__ alignas(16) uint8_t dirb[4096];
-  const int j = blockIdx.x;
-  if (j >= njobs) return;
-  const JobDev &jd = jobs[j];
+  const JobDev *__restrict__ jobs = a->jobs;
+  const int njobs = __builtin_amdgcn_readfirstlane(a->njobs);
   const int gst = __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int jst = __hip_atomic_load(jd.jstatus, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int st = gst != ST_OK ? gst : jst;
-  switch (jd.k) {
-    case 2: if constexpr (KLO <= 2 && 2 <= KHI) traceback_job<2>(jd, st, dirb); break;
-    case 3: if constexpr (KLO <= 3 && 3 <= KHI) traceback_job<3>(jd, st, dirb); break;
-    case 4: if constexpr (KLO <= 4 && 4 <= KHI) traceback_job<4>(jd, st, dirb); break;
-    case 5: if constexpr (KLO <= 5 && 5 <= KHI) traceback_job<5>(jd, st, dirb); break;
-    case 6: if constexpr (KLO <= 6 && 6 <= KHI) traceback_job<6>(jd, st, dirb); break;
-    case 7: if constexpr (KLO <= 7 && 7 <= KHI) traceback_job<7>(jd, st, dirb); break;
-    case 8: if constexpr (KLO <= 8 && 8 <= KHI) traceback_job<8>(jd, st, dirb); break;
-    default: break;
+  for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
+    const JobDev &jd = jobs[j];
+    const int jst = __hip_atomic_load(jd.jstatus, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int st = gst != ST_OK ? gst : jst;
+    switch (jd.k) {
+      case 2: if constexpr (KLO <= 2 && 2 <= KHI) traceback_job<2>(jd, st, dirb); break;
+      case 3: if constexpr (KLO <= 3 && 3 <= KHI) traceback_job<3>(jd, st, dirb); break;
+      case 4: if constexpr (KLO <= 4 && 4 <= KHI) traceback_job<4>(jd, st, dirb); break;
+      case 5: if constexpr (KLO <= 5 && 5 <= KHI) traceback_job<5>(jd, st, dirb); break;
+      case 6: if constexpr (KLO <= 6 && 6 <= KHI) traceback_job<6>(jd, st, dirb); break;
+      case 7: if constexpr (KLO <= 7 && 7 <= KHI) traceback_job<7>(jd, st, dirb); break;
+      case 8: if constexpr (KLO <= 8 && 8 <= KHI) traceback_job<8>(jd, st, dirb); break;
+      default: break;
+    }
   }
 }
 
 // Clears the completion flags of a launch (a kernel, not a memset, so that the
 // launch sequence can be captured in a graph).
-__global__ void batch_zero_kernel(int32_t *flags, int64_t n) {
+__global__ void batch_zero_kernel(const BatchArgs *__restrict__ a) {
+  int32_t *flags = a->flags;
+  const int64_t n = a->tiles;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     flags[i] = 0;
@@ -1811,42 +1821,30 @@ int launch_export(const JobDev &jd, const Ctrl *ctrl, uint8_t *out, int64_t ncel
 namespace msa {
 
 constexpr int kBatchThreads = 256;
+// Fixed grids of the launch sequence (it is replayed from a graph for every
+// batch): the flag-clearing and queue kernels stride over the tiles and
+// columns, the traceback over the jobs, one wave per job at a time.
+constexpr int kBatchAuxGrid = 1024;
+constexpr int kBatchTraceGrid = 4096;
 
 template <int KLO, int KHI>
-static int launch_batch_k(const JobDev *d_jobs, int njobs, const int64_t *d_jcols,
-                          int32_t *qjob, int32_t *qtile, int64_t tiles, int64_t cols,
-                          int32_t *flags, Ctrl *ctrl, int grid, hipStream_t s) {
-  int64_t qb = (tiles + 255) / 256;
-  if (qb > 8192) qb = 8192;
-  if (qb < 1) qb = 1;
-  hipLaunchKernelGGL(batch_zero_kernel, dim3((unsigned)qb), dim3(256), 0, s, flags, tiles);
-  hipLaunchKernelGGL(batch_queue_kernel, dim3((unsigned)qb), dim3(256), 0, s, d_jobs, njobs,
-                     d_jcols, qjob, qtile);
-  if (grid > cols) grid = (int)(cols > 0 ? cols : 1);
+static int launch_batch_k(const BatchArgs *d_args, Ctrl *ctrl, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(batch_zero_kernel, dim3(kBatchAuxGrid), dim3(256), 0, s, d_args);
+  hipLaunchKernelGGL(batch_queue_kernel, dim3(kBatchAuxGrid), dim3(256), 0, s, d_args);
   hipLaunchKernelGGL((batch_fill_kernel<KLO, KHI, kBatchThreads>), dim3(grid),
-                     dim3(kBatchThreads), 0, s, d_jobs, qjob, qtile, (int32_t)cols, ctrl);
-  hipLaunchKernelGGL((batch_traceback_kernel<KLO, KHI>), dim3(njobs), dim3(64), 0, s, d_jobs,
-                     njobs, ctrl);
+                     dim3(kBatchThreads), 0, s, d_args, ctrl);
+  hipLaunchKernelGGL((batch_traceback_kernel<KLO, KHI>), dim3(kBatchTraceGrid), dim3(64), 0, s,
+                     d_args, ctrl);
   hipLaunchKernelGGL(batch_finish_kernel, dim3(1), dim3(64), 0, s, ctrl);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_jcols,
-                 int32_t *qjob, int32_t *qtile, int64_t tiles, int64_t cols, int32_t *flags,
-                 Ctrl *ctrl, int grid, hipStream_t s) {
+int launch_batch(int kclass, const BatchArgs *d_args, Ctrl *ctrl, int grid, hipStream_t s) {
   switch (kclass) {
-    case 0:
-      return launch_batch_k<2, 4>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
-                                  grid, s);
-    case 1:
-      return launch_batch_k<5, 5>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
-                                  grid, s);
-    case 2:
-      return launch_batch_k<6, 6>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
-                                  grid, s);
-    default:
-      return launch_batch_k<7, 8>(d_jobs, njobs, d_jcols, qjob, qtile, tiles, cols, flags, ctrl,
-                                  grid, s);
+    case 0: return launch_batch_k<2, 4>(d_args, ctrl, grid, s);
+    case 1: return launch_batch_k<5, 5>(d_args, ctrl, grid, s);
+    case 2: return launch_batch_k<6, 6>(d_args, ctrl, grid, s);
+    default: return launch_batch_k<7, 8>(d_args, ctrl, grid, s);
   }
 }
 

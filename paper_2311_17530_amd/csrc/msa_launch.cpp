@@ -12,6 +12,10 @@ namespace msa {
 
 static int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
+// The batch descriptor sits right after the control block in every arena.
+constexpr int64_t kArgsOff = 256;
+static_assert(sizeof(Ctrl) <= kArgsOff, "control block first");
+
 int validate_job(const msa_job &j, int64_t) {
   if (j.k < 2 || j.k > MSA_MAX_K) return MSA_EINVAL;
   if (!j.submat || j.alpha < 1 || j.alpha > 255) return MSA_EINVAL;
@@ -67,12 +71,13 @@ int64_t Launch::overhead_bytes(int njobs, int64_t ntiles_total) {
     const int T = tile_edge_for_k(k);
     tables += a256((int64_t)ipow(T, k) * 4) + a256((int64_t)(k * (T - 1) + 2) * 4);
   }
-  return 256 + tables + a256((int64_t)njobs * sizeof(JobDev)) + a256((int64_t)(njobs + 1) * 8) +
+  return 512 + tables + a256((int64_t)njobs * sizeof(JobDev)) + a256((int64_t)(njobs + 1) * 8) +
          a256((int64_t)njobs * 24) + 3 * a256(ntiles_total * 4) + 255 * 255 * 4 + 4096;
 }
 
 Launch::~Launch() {
   if (busy_) wait();
+  drop_graphs();
   if (d_) (void)hipFree(d_);
   if (h_in_) (void)hipHostFree(h_in_);
   if (h_out_) (void)hipHostFree(h_out_);
@@ -90,6 +95,7 @@ int Launch::init(int64_t bytes) {
   if (!start_ && hipEventCreateWithFlags(&start_, hipEventDefault) != hipSuccess)
     return MSA_EDEVICE;
   if (cap_ < bytes) {
+    drop_graphs();  // they hold addresses inside the old arena
     if (d_) (void)hipFree(d_);
     d_ = nullptr;
     cap_ = 0;
@@ -100,6 +106,37 @@ int Launch::init(int64_t bytes) {
     cap_ = bytes;
   }
   return MSA_OK;
+}
+
+void Launch::drop_graphs() {
+  for (int kc = 0; kc < 4; ++kc) {
+    if (graph_[kc]) (void)hipGraphExecDestroy(graph_[kc]);
+    graph_[kc] = nullptr;
+    graph_failed_[kc] = false;
+  }
+}
+
+// Captures the launch sequence of k class kc on this arena.  Returns 0 when
+// a graph is ready; otherwise the caller launches the kernels directly.
+int Launch::ensure_graph(int kc, int grid) {
+  if (graph_[kc]) return 0;
+  if (graph_failed_[kc]) return -1;
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    const int rc = launch_batch(kc, reinterpret_cast<const BatchArgs *>(d_ + kArgsOff),
+                                reinterpret_cast<Ctrl *>(d_), grid, stream_);
+    ok = hipStreamEndCapture(stream_, &g) == hipSuccess && rc == 0 && g;
+  }
+  ok = ok && hipGraphInstantiate(&graph_[kc], g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (!ok) {
+    graph_[kc] = nullptr;
+    graph_failed_[kc] = true;
+    (void)hipGetLastError();  // clear a capture error; the direct launches follow
+    return -1;
+  }
+  return 0;
 }
 
 int Launch::ensure_host(int64_t in_bytes, int64_t out_bytes) {
@@ -142,6 +179,8 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   // ---- layout: [inputs (one host-to-device copy)][outputs][device only] ----
   int64_t o = 0;
   const int64_t off_ctrl = o;  o += 256;
+  const int64_t off_args = o;  o = a256(o + (int64_t)sizeof(BatchArgs));
+  if (off_args != kArgsOff) return MSA_EINVAL;
   const int64_t off_jobs = o;  o = a256(o + (int64_t)nj * sizeof(JobDev));
   const int64_t off_jt = o;    o = a256(o + (int64_t)(nj + 1) * 8);
   const int64_t off_jc = o;    o = a256(o + (int64_t)(nj + 1) * 8);
@@ -292,17 +331,30 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
       }
   }
 
-  // ---- enqueue ----
-  bool ok = hipEventRecord(start_, stream_) == hipSuccess;
-  ok = ok && hipMemcpyAsync(d_, h, (size_t)in_bytes, hipMemcpyHostToDevice, stream_) == hipSuccess;
+  // ---- batch descriptor (read by the launch sequence) ----
+  BatchArgs args;
+  memset(&args, 0, sizeof(args));
+  args.jobs = reinterpret_cast<const JobDev *>(d_ + off_jobs);
+  args.jcols = reinterpret_cast<const int64_t *>(d_ + off_jc);
+  args.qjob = reinterpret_cast<int32_t *>(d_ + off_qjob);
+  args.qtile = reinterpret_cast<int32_t *>(d_ + off_qtile);
+  args.flags = reinterpret_cast<int32_t *>(d_ + off_flags);
+  args.tiles = tiles;
+  args.cols = jc[nj];
+  args.njobs = nj;
+  memcpy(h + off_args, &args, sizeof(args));
+
+  // ---- enqueue: inputs, the launch sequence (a graph replay), outputs ----
   int grid = device_cu_count() * batch_occupancy(kc);
   if (grid < 1) grid = 1;
-  ok = ok && launch_batch(kc, reinterpret_cast<const JobDev *>(d_ + off_jobs), nj,
-                          reinterpret_cast<const int64_t *>(d_ + off_jc),
-                          reinterpret_cast<int32_t *>(d_ + off_qjob),
-                          reinterpret_cast<int32_t *>(d_ + off_qtile), tiles, jc[nj],
-                          reinterpret_cast<int32_t *>(d_ + off_flags),
-                          reinterpret_cast<Ctrl *>(d_ + off_ctrl), grid, stream_) == 0;
+  const bool graph = ensure_graph(kc, grid) == 0;
+  bool ok = hipEventRecord(start_, stream_) == hipSuccess;
+  ok = ok && hipMemcpyAsync(d_, h, (size_t)in_bytes, hipMemcpyHostToDevice, stream_) == hipSuccess;
+  if (graph)
+    ok = ok && hipGraphLaunch(graph_[kc], stream_) == hipSuccess;
+  else
+    ok = ok && launch_batch(kc, reinterpret_cast<const BatchArgs *>(d_ + off_args),
+                            reinterpret_cast<Ctrl *>(d_ + off_ctrl), grid, stream_) == 0;
   ok = ok && hipMemcpyAsync(h_out_, d_ + off_out, (size_t)out_bytes, hipMemcpyDeviceToHost,
                             stream_) == hipSuccess;
   ok = ok && hipEventRecord(done_, stream_) == hipSuccess;

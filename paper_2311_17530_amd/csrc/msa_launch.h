@@ -85,7 +85,14 @@ class Launch {
   std::vector<Meta> meta_;
   bool busy_ = false;
   int launch_status_ = MSA_OK;
+  // The launch sequence of each k class, captured once on this arena (its
+  // arguments are the arena's fixed batch descriptor and control block) and
+  // replayed for every batch; dropped when the arena is reallocated.
+  hipGraphExec_t graph_[4] = {};
+  bool graph_failed_[4] = {};
   int ensure_host(int64_t in_bytes, int64_t out_bytes);
+  int ensure_graph(int kc, int grid);
+  void drop_graphs();
 };
 
 }  // namespace msa

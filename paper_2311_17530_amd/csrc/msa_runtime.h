@@ -24,9 +24,10 @@ int fill_occupancy(int k);
 int launch_prune_bounds(const PruneDev &pd, Ctrl *ctrl, hipStream_t s);
 int launch_prune_select(const PruneDev &pd, Ctrl *ctrl, int pass, hipStream_t s);
 int launch_prune_check(const PruneDev &pd, Ctrl *ctrl, hipStream_t s);
-int launch_batch(int kclass, const JobDev *d_jobs, int njobs, const int64_t *d_jcols,
-                 int32_t *qjob, int32_t *qtile, int64_t tiles, int64_t cols, int32_t *flags,
-                 Ctrl *ctrl, int grid, hipStream_t s);
+// The batched launch sequence (flag clearing, queue, fill, traceback, control
+// block reset) for the batch described by d_args; grid workgroups for the
+// persistent fill.  Fixed arguments only, so it can be captured in a graph.
+int launch_batch(int kclass, const BatchArgs *d_args, Ctrl *ctrl, int grid, hipStream_t s);
 int batch_occupancy(int kclass);
 // streaming k = 3 fill (msa_sweep3.hip), for plans with sweep3_eligible
 int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, hipStream_t s);

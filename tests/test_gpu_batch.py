@@ -85,6 +85,31 @@ def test_batch_matches_oracle_and_plain_path():
         assert s1 == score and np.array_equal(r1, rows)
 
 
+def test_batch_graph_replays_and_permuted_queue_order():
+    # Every batched launch replays the launch sequence captured once per arena
+    # and k class.  Replays with other device work and synchronisations in
+    # between give the plain path's bytes, batch after batch and for batches
+    # of other sizes, and so does any order of the jobs: jobs of equal k and
+    # scoring keep the caller's order, so a permutation reorders the column
+    # queue inside every computation wave.
+    import torch
+    jobs = small_mixed(5100, 60)
+    plain = [msa.align(*j) for j in jobs]
+    rng = np.random.Generator(np.random.PCG64(5101))
+    for rep, size in enumerate((60, 60, 60, 7, 1, 33)):
+        perm = rng.permutation(len(jobs)) if rep else np.arange(len(jobs))
+        perm = perm[:size]
+        say("batch replay", rep, "jobs", size)
+        res = msa.align_batch([jobs[i] for i in perm])
+        assert len(res) == size
+        for i, (st, score, rows) in zip(perm, res):
+            assert st == msa.MSA_OK
+            assert score == plain[i][0] and np.array_equal(rows, plain[i][1]), (rep, int(i))
+        s, r = msa.align(*jobs[rep])  # eager work between the replays
+        torch.cuda.synchronize()
+        assert s == plain[rep][0] and np.array_equal(r, plain[rep][1])
+
+
 def test_batch_small_budget_splits_launches():
     jobs = small_mixed(5001, 30)
     say("batch with small budget")
