@@ -63,6 +63,44 @@ enum {
 #define MSA_PRUNE 4u         /* exact tile pruning, see msa_dp_align_ex */
 #define MSA_NEAROPT 8u       /* cell scores kept for msa_dp_nearopt_dev */
 
+/* ------------------------------------------------------------------------
+ * Launch-configuration tuner.  Per (architecture of the current device,
+ * kind, k, length bucket) a table holds the fill variant and the number of
+ * workgroups per compute unit that later calls use; every configuration
+ * computes the same bytes, only the time differs.  Buckets: the plain path
+ * keys by k and ceil(log2(longest length + 1)); the batched path by k class
+ * (k = 2..4, 5, 6, 7..8).  Thread-safe; the table lives for the process.
+ *   kind    : MSA_TUNE_PLAIN or MSA_TUNE_BATCH
+ *   variant : plain path: 0 the built-in rule, 1 the streaming k = 3 fill
+ *             (used only where it applies), 2 the tile fill; batched: 0
+ *   wpc     : workgroups per compute unit of the tile fill or the batched
+ *             fill (capped at what fits); 0 the built-in rule
+ * msa_dp_tune_set stores a choice, msa_dp_tune_get reads it ((0, 0) when
+ * none is stored) into choice_out[2], msa_dp_tune_clear empties the table.
+ * msa_dp_tune_candidates writes up to cap / 2 (variant, wpc) pairs the tuner
+ * tries for that key and returns their number.
+ * msa_dp_autotune times the fill of every candidate on a device workspace of
+ * the given shape and scoring (seeded residues; `reps` timed fills each,
+ * median, HIP events), stores the fastest and returns it in choice_out[2]
+ * (and its time in *best_ms_out when not NULL).  It allocates a workspace of
+ * msa_dp_workspace_bytes(lens, k) bytes for the duration of the call.
+ * msa_dp_autotune_batch runs msa_dp_align_batch on the jobs of each k class
+ * present with every candidate workgroup count (`reps` timed runs each,
+ * median wall time) and stores the fastest; wpc_out[4] receives the choice
+ * per k class (0 for classes not present).
+ * Errors: MSA_EINVAL for bad arguments, the errors of msa_dp_align /
+ * msa_dp_align_batch, MSA_EDEVICE.
+ * ---------------------------------------------------------------------- */
+#define MSA_TUNE_PLAIN 0
+#define MSA_TUNE_BATCH 1
+int msa_dp_tune_set(int32_t kind, int32_t k, int32_t max_len, int32_t variant, int32_t wpc);
+int msa_dp_tune_get(int32_t kind, int32_t k, int32_t max_len, int32_t *choice_out);
+void msa_dp_tune_clear(void);
+int msa_dp_tune_candidates(int32_t kind, int32_t k, int32_t max_len, int32_t *out,
+                           int32_t cap);
+int msa_dp_autotune(const int32_t *lens, int32_t k, const int8_t *submat, int32_t alpha,
+                    int32_t gap, int32_t reps, int32_t *choice_out, float *best_ms_out);
+
 /* Human-readable text for a status code (static storage). */
 const char *msa_strerror(int status);
 
@@ -345,6 +383,9 @@ typedef struct {
 
 int msa_dp_align_batch(const msa_job *jobs, int32_t njobs,
                        msa_result *results, int64_t hbm_budget_bytes);
+
+/* The batched half of the tuner (see msa_dp_autotune above). */
+int msa_dp_autotune_batch(const msa_job *jobs, int32_t njobs, int32_t reps, int32_t *wpc_out);
 
 /* ------------------------------------------------------------------------
  * Served path: a request loop that admits jobs as device memory (the HBM

@@ -60,6 +60,9 @@ MSA_END_GAPS_FREE = 1
 MSA_COOPTIMAL = 2
 MSA_PRUNE = 4
 MSA_NEAROPT = 8
+# launch-configuration tuner kinds
+MSA_TUNE_PLAIN = 0
+MSA_TUNE_BATCH = 1
 
 _SIGS = {
     "msa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -116,6 +119,17 @@ _SIGS = {
                                            ctypes.c_int32, c_i64p, c_i64p]),
     "msa_dp_check_scoring": (ctypes.c_int, [c_i32p, ctypes.c_int32, c_vp, ctypes.c_int32,
                                             ctypes.c_int32, ctypes.c_uint32]),
+    "msa_dp_tune_set": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32]),
+    "msa_dp_tune_get": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, c_i32p]),
+    "msa_dp_tune_clear": (None, []),
+    "msa_dp_tune_candidates": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              c_i32p, ctypes.c_int32]),
+    "msa_dp_autotune": (ctypes.c_int, [c_i32p, ctypes.c_int32, c_vp, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, c_i32p,
+                                       ctypes.POINTER(ctypes.c_float)]),
+    "msa_dp_autotune_batch": (ctypes.c_int, [ctypes.POINTER(MsaJob), ctypes.c_int32,
+                                             ctypes.c_int32, c_i32p]),
     "msa_dp_tile_edge": (ctypes.c_int32, [ctypes.c_int32]),
     "msa_dp_tile_grid": (ctypes.c_int32, [c_i32p, ctypes.c_int32, ctypes.c_int32, c_i32p]),
     "msa_dp_wave_counts": (ctypes.c_int32, [c_i32p, ctypes.c_int32, c_i64p, ctypes.c_int32]),
@@ -288,6 +302,55 @@ def workspace_bytes_ex(lens, flags: int) -> int:
     if n < 0:
         raise MsaError(int(n), "msa_dp_workspace_bytes_ex")
     return int(n)
+
+
+def tune_set(kind: int, k: int, max_len: int, variant: int, wpc: int):
+    """Store a launch configuration for (kind, k, length bucket of max_len)
+    (``msa_dp_tune_set``)."""
+    _check(lib().msa_dp_tune_set(int(kind), int(k), int(max_len), int(variant), int(wpc)),
+           "msa_dp_tune_set")
+
+
+def tune_get(kind: int, k: int, max_len: int):
+    """``(variant, wpc)`` stored for the key, (0, 0) for the built-in rule."""
+    out = (ctypes.c_int32 * 2)()
+    _check(lib().msa_dp_tune_get(int(kind), int(k), int(max_len), out), "msa_dp_tune_get")
+    return int(out[0]), int(out[1])
+
+
+def tune_clear():
+    lib().msa_dp_tune_clear()
+
+
+def tune_candidates(kind: int, k: int, max_len: int):
+    """The (variant, wpc) pairs the tuner tries for the key."""
+    n = lib().msa_dp_tune_candidates(int(kind), int(k), int(max_len), None, 0)
+    if n < 0:
+        raise MsaError(int(n), "msa_dp_tune_candidates")
+    out = (ctypes.c_int32 * (2 * n))()
+    lib().msa_dp_tune_candidates(int(kind), int(k), int(max_len), out, 2 * n)
+    return [(int(out[2 * i]), int(out[2 * i + 1])) for i in range(n)]
+
+
+def autotune(lens, sub, gap, reps: int = 3):
+    """Time every candidate fill of this shape (``msa_dp_autotune``), store the
+    fastest and return ``(variant, wpc, best_ms)``."""
+    sub = np.ascontiguousarray(np.asarray(sub, dtype=np.int8))
+    out = (ctypes.c_int32 * 2)()
+    ms = ctypes.c_float()
+    _check(lib().msa_dp_autotune(_i32arr(lens), len(lens), sub.ctypes.data, sub.shape[0],
+                                 int(gap), int(reps), out, ctypes.byref(ms)), "msa_dp_autotune")
+    return int(out[0]), int(out[1]), float(ms.value)
+
+
+def autotune_batch(jobs, reps: int = 2):
+    """Time every candidate workgroup count of the batched fill on these jobs
+    (``msa_dp_autotune_batch``); returns the choice per k class."""
+    keep = []
+    arr = (MsaJob * len(jobs))(*[_make_job(s, m, g, keep) for s, m, g in jobs])
+    out = (ctypes.c_int32 * 4)()
+    _check(lib().msa_dp_autotune_batch(arr, len(jobs), int(reps), out), "msa_dp_autotune_batch")
+    return [int(x) for x in out]
 
 
 # ---------------------------------------------------------------------------

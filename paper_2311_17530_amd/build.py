@@ -28,7 +28,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wno-unused-but-set-variable"]
 
 SOURCES = ["msa_kernels.hip", "msa_sweep3.hip", "msa_prune.hip", "msa_static.hip", "msa_plan.cpp", "msa_launch.cpp",
-           "msa_runtime.cpp", "msa_abi.cpp", "msa_batch.cpp", "msa_server.cpp"]
+           "msa_runtime.cpp", "msa_abi.cpp", "msa_batch.cpp", "msa_server.cpp",
+           "msa_tune.cpp"]
 
 
 def _compile(src: Path, obj: Path, extra=()) -> None:

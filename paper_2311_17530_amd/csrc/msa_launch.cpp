@@ -7,6 +7,7 @@
 #include <map>
 
 #include "msa_runtime.h"
+#include "msa_tune.h"
 
 namespace msa {
 
@@ -119,8 +120,13 @@ void Launch::drop_graphs() {
 // Captures the launch sequence of k class kc on this arena.  Returns 0 when
 // a graph is ready; otherwise the caller launches the kernels directly.
 int Launch::ensure_graph(int kc, int grid) {
+  if (graph_[kc] && graph_grid_[kc] != grid) {  // another tuned grid: capture again
+    (void)hipGraphExecDestroy(graph_[kc]);
+    graph_[kc] = nullptr;
+  }
   if (graph_[kc]) return 0;
   if (graph_failed_[kc]) return -1;
+  graph_grid_[kc] = grid;
   hipGraph_t g = nullptr;
   bool ok = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
@@ -345,7 +351,11 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   memcpy(h + off_args, &args, sizeof(args));
 
   // ---- enqueue: inputs, the launch sequence (a graph replay), outputs ----
-  int grid = device_cu_count() * batch_occupancy(kc);
+  // persistent workgroups: every one that fits, or the tuned count per CU
+  int wpc = batch_occupancy(kc);
+  TuneChoice tc;
+  if (tune_get(kTuneBatch, kc, 0, &tc) && tc.wpc > 0) wpc = std::min(wpc, (int)tc.wpc);
+  int grid = device_cu_count() * wpc;
   if (grid < 1) grid = 1;
   const bool graph = ensure_graph(kc, grid) == 0;
   bool ok = hipEventRecord(start_, stream_) == hipSuccess;

@@ -89,6 +89,7 @@ class Launch {
   // arguments are the arena's fixed batch descriptor and control block) and
   // replayed for every batch; dropped when the arena is reallocated.
   hipGraphExec_t graph_[4] = {};
+  int graph_grid_[4] = {};  // the fill grid each graph was captured with
   bool graph_failed_[4] = {};
   int ensure_host(int64_t in_bytes, int64_t out_bytes);
   int ensure_graph(int kc, int grid);

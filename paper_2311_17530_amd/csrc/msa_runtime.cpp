@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/msa_dp.h"
+#include "msa_tune.h"
 
 namespace msa {
 
@@ -44,6 +45,11 @@ int device_cu_count() {
     g_cu[dev] = n;
   }
   return g_cu[dev];
+}
+
+void forget_workspace(const char *ws) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_ws.erase((uintptr_t)ws);
 }
 
 int32_t workspace_flags(const char *ws) {
@@ -128,20 +134,16 @@ static int64_t *g_trace_buf = nullptr;
 extern "C" void msa_dp_debug_set_trace(int64_t *d_buf) { g_trace_buf = d_buf; }
 #endif
 
-static int fill_grid(const Plan &p) {
+static int fill_grid(const Plan &p, int wpc) {
   // Persistent workgroups: as many tiles as the widest wave holds, rounded
   // down to whole compute units, at least one per unit and at most what
   // fits.  Beyond the widest wave extra workgroups only wait, and tiles that
   // share a compute unit slow each other's sweep, which is the critical path.
+  // A tuned choice (wpc > 0) fixes the workgroups per compute unit instead.
   const int64_t cu = device_cu_count();
   int64_t grid = p.max_wave / cu * cu;
   if (grid < cu) grid = cu;
-  // MSA_WG_PER_CU (tuning): a fixed number of workgroups per compute unit
-  static const int wg_env = [] {
-    const char *e = getenv("MSA_WG_PER_CU");
-    return e ? atoi(e) : 0;
-  }();
-  if (wg_env > 0) grid = cu * wg_env;
+  if (wpc > 0) grid = cu * wpc;
   if (grid > cu * occupancy(p.k)) grid = cu * occupancy(p.k);
   if (grid > p.ntiles) grid = p.ntiles;
   if (grid < 1) grid = 1;
@@ -153,9 +155,12 @@ static int fill_grid(const Plan &p) {
 // selection and two-pass sequence of msa_prune.hip.
 static int run_fill(const Plan &p, char *ws, JobDev &jd, hipStream_t s, int alpha) {
   Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
-  if (sweep3_eligible(p, alpha, workspace_flags(ws))) return launch_sweep3(p, ws, jd, ctrl, s);
+  TuneChoice tc;
+  tune_get(kTunePlain, p.k, length_bucket(p.n, p.k), &tc);
+  if (tc.variant != 2 && sweep3_eligible(p, alpha, workspace_flags(ws)))
+    return launch_sweep3(p, ws, jd, ctrl, s);
   const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
-  int grid = fill_grid(p);
+  int grid = fill_grid(p, tc.variant == 2 ? tc.wpc : 0);
   if (jd.ncols > 0 && grid > jd.ncols) grid = jd.ncols;
   if (!(workspace_flags(ws) & kPrune)) return launch_fill(jd, ctrl, order, grid, 0, s);
   PruneDev pd;

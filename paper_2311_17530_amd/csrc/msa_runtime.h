@@ -34,6 +34,8 @@ int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, hipStre
 
 // runtime (msa_runtime.cpp)
 int device_cu_count();
+// drops what prepare_workspace recorded for `ws` (before its memory is freed)
+void forget_workspace(const char *ws);
 // mode flags given to prepare_workspace for the workspace at `ws` (0 if none)
 int32_t workspace_flags(const char *ws);
 // MSA_OK when `ws` was prepared for the shape of `p` (and its alphabet size

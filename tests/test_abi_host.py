@@ -307,3 +307,24 @@ def test_nearopt_limits_and_workspace_before_device():
     rc = msa.lib().msa_dp_prepare_ex(ws, plain, lens, 3, sub8.ctypes.data, 4, gap,
                                      msa.MSA_NEAROPT, None)
     assert rc == msa.MSA_EINVAL
+
+
+def test_tuner_table_without_device():
+    # the table keys by (architecture, kind, k, length bucket); a bucket holds
+    # longest lengths 2^(b-1) .. 2^b - 1; no device is touched
+    msa.tune_clear()
+    assert msa.tune_get(msa.MSA_TUNE_PLAIN, 3, 512) == (0, 0)
+    msa.tune_set(msa.MSA_TUNE_PLAIN, 3, 512, 2, 3)
+    assert msa.tune_get(msa.MSA_TUNE_PLAIN, 3, 1023) == (2, 3)
+    assert msa.tune_get(msa.MSA_TUNE_PLAIN, 3, 511) == (0, 0)
+    assert msa.tune_get(msa.MSA_TUNE_PLAIN, 4, 512) == (0, 0)
+    msa.tune_set(msa.MSA_TUNE_BATCH, 3, 0, 0, 2)  # the class of k = 2..4
+    assert msa.tune_get(msa.MSA_TUNE_BATCH, 2, 7) == (0, 2)
+    assert msa.tune_get(msa.MSA_TUNE_BATCH, 5, 0) == (0, 0)
+    for args in ((2, 3, 10, 0, 0), (0, 9, 10, 0, 0), (0, 3, -1, 0, 0), (0, 3, 10, 3, 0),
+                 (0, 3, 10, 1, 65), (1, 3, 10, 1, 1)):
+        with pytest.raises(msa.MsaError) as e:
+            msa.tune_set(*args)
+        assert e.value.status == msa.MSA_EINVAL
+    msa.tune_clear()
+    assert msa.tune_get(msa.MSA_TUNE_PLAIN, 3, 512) == (0, 0)

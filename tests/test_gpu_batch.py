@@ -200,7 +200,13 @@ def test_server_stream_of_served_jobs():
         for j in jobs:
             tickets.append(srv.submit(j.seqs, j.sub, j.gap))
         out = [srv.wait(t, 60_000_000) for t in tickets]
-    assert all(o is not None and o[0] == msa.MSA_OK for o in out)
+        stats = srv.stats()
+    bad = {}
+    for i, o in enumerate(out):
+        if o is None or o[0] != msa.MSA_OK:
+            key = "timeout" if o is None else o[0]
+            bad.setdefault(key, []).append(i)
+    assert not bad, ({s: (len(v), v[:8]) for s, v in bad.items()}, stats)
     t0 = time.time()
     equal = 0
     for j, (_, score, rows) in zip(jobs, out):
