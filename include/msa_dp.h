@@ -420,8 +420,9 @@ void msa_server_destroy(msa_server *srv);
  * busy time in microseconds (the union of the completed launches' device
  * intervals, each from its input copy to its output copy, measured with HIP
  * events), [3] span in microseconds from the first launch's start to the
- * last launch's end, [4] jobs queued and not yet admitted.  Returns MSA_OK
- * or MSA_EINVAL. */
+ * last launch's end, [4] jobs queued and not yet admitted, [5] jobs that
+ * ended with a status other than MSA_OK, [6] the last such status (MSA_OK if
+ * none).  Returns MSA_OK or MSA_EINVAL. */
 int msa_server_stats(msa_server *srv, int64_t *out, int32_t n);
 
 /* ------------------------------------------------------------------------

@@ -606,11 +606,12 @@ class Server:
         return self._result(ticket, timeout_us)
 
     def stats(self):
-        """``{"launches", "jobs", "busy_us", "span_us", "queued"}`` so far."""
-        out = (ctypes.c_int64 * 5)()
-        _check(lib().msa_server_stats(self.h, out, 5), "msa_server_stats")
-        return dict(zip(("launches", "jobs", "busy_us", "span_us", "queued"),
-                        [int(x) for x in out]))
+        """``{"launches", "jobs", "busy_us", "span_us", "queued", "failed",
+        "last_failure"}`` so far."""
+        out = (ctypes.c_int64 * 7)()
+        _check(lib().msa_server_stats(self.h, out, 7), "msa_server_stats")
+        return dict(zip(("launches", "jobs", "busy_us", "span_us", "queued", "failed",
+                         "last_failure"), [int(x) for x in out]))
 
     def close(self):
         if self.h:

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -76,12 +77,27 @@ struct msa_server {
   // interval (ms after `ref`, recorded at creation) for the busy time
   hipEvent_t ref = nullptr;
   int64_t n_launches = 0, n_jobs = 0;
+  // jobs that ended with a status other than MSA_OK, and the last such status
+  int64_t n_failed = 0;
+  int32_t last_failure = MSA_OK;
   std::vector<std::pair<float, float>> intervals;
 
   void run();
   bool admit(Slot &s, int free_slots);
   void collect(Slot &s);
+  void note_failure(int32_t status, int64_t jobs, const char *where);
 };
+
+// Failed jobs are counted (msa_server_stats) and the first few failures are
+// reported on stderr with where they arose, so that a failure seen under
+// load can be told apart from the others.
+void msa_server::note_failure(int32_t status, int64_t jobs, const char *where) {
+  n_failed += jobs;
+  last_failure = status;
+  if (n_failed - jobs < 8)
+    fprintf(stderr, "msa server: %lld job(s) ended with status %d (%s)\n", (long long)jobs,
+            (int)status, where);
+}
 
 bool msa_server::admit(Slot &s, int free_slots) {
   // FIFO admission: the oldest job fixes the k class; later jobs of the same
@@ -123,6 +139,7 @@ bool msa_server::admit(Slot &s, int free_slots) {
   const int rc = s.launch->start(grp);
   for (uint64_t t : s.tickets) running[t] = 0;
   if (rc != MSA_OK) {
+    note_failure(rc, (int64_t)s.tickets.size(), "launch set-up");
     for (uint64_t t : s.tickets) {
       done[t].status = rc;
       running.erase(t);
@@ -147,6 +164,7 @@ void msa_server::collect(Slot &s) {
     s.launch->result((int)i, &r);
     Done &d = done[s.tickets[i]];
     d.status = r.status;
+    if (r.status != MSA_OK) note_failure(r.status, 1, "launch result");
     d.score = r.score;
     d.aln_len = r.aln_len;
     d.k = r.k;
@@ -328,10 +346,10 @@ extern "C" int msa_server_stats(msa_server *srv, int64_t *out, int32_t n) {
     last = std::max(last, (double)x.second);
   }
   if (open) busy += hi - lo;
-  const int64_t v[5] = {srv->n_launches, srv->n_jobs, (int64_t)(busy * 1000.0),
+  const int64_t v[7] = {srv->n_launches, srv->n_jobs, (int64_t)(busy * 1000.0),
                         open ? (int64_t)((last - first) * 1000.0) : 0,
-                        (int64_t)srv->queue.size()};
-  for (int i = 0; i < n && i < 5; ++i) out[i] = v[i];
+                        (int64_t)srv->queue.size(), srv->n_failed, srv->last_failure};
+  for (int i = 0; i < n && i < 7; ++i) out[i] = v[i];
   return MSA_OK;
 }
 
