@@ -422,7 +422,10 @@ void msa_server_destroy(msa_server *srv);
  * events), [3] span in microseconds from the first launch's start to the
  * last launch's end, [4] jobs queued and not yet admitted, [5] jobs that
  * ended with a status other than MSA_OK, [6] the last such status (MSA_OK if
- * none).  Returns MSA_OK or MSA_EINVAL. */
+ * none), [7] the longest pause in microseconds that a launch's fill saw
+ * between two checks of a dependency wait, that is a time its queue did not
+ * run (0 if none; such pauses do not count towards the wait's 2 s time-out).
+ * Returns MSA_OK or MSA_EINVAL. */
 int msa_server_stats(msa_server *srv, int64_t *out, int32_t n);
 
 /* ------------------------------------------------------------------------

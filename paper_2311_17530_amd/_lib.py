@@ -607,11 +607,11 @@ class Server:
 
     def stats(self):
         """``{"launches", "jobs", "busy_us", "span_us", "queued", "failed",
-        "last_failure"}`` so far."""
-        out = (ctypes.c_int64 * 7)()
-        _check(lib().msa_server_stats(self.h, out, 7), "msa_server_stats")
+        "last_failure", "max_pause_us"}`` so far."""
+        out = (ctypes.c_int64 * 8)()
+        _check(lib().msa_server_stats(self.h, out, 8), "msa_server_stats")
         return dict(zip(("launches", "jobs", "busy_us", "span_us", "queued", "failed",
-                         "last_failure"), [int(x) for x in out]))
+                         "last_failure", "max_pause_us"), [int(x) for x in out]))
 
     def close(self):
         if self.h:

@@ -13,9 +13,17 @@
 // belongs to exactly one tile, so the fill needs no special boundary code:
 // an out-of-range neighbour reads -infinity and never wins.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace msa {
+
+// HIP keeps one last-error code per host thread until it is read.  A
+// launcher clears it right before its launches, so that what it reads
+// afterwards comes from those launches and not from an earlier call of the
+// same thread: launch_begin() ... launch_end() (0 or -1).
+inline void launch_begin() { (void)hipGetLastError(); }
+inline int launch_end() { return hipGetLastError() == hipSuccess ? 0 : -1; }
 
 constexpr int kMaxK = 8;
 constexpr int kNegKey = -(1 << 30);  // "-infinity" key; see range check
@@ -76,9 +84,42 @@ struct Ctrl {
   int64_t prune_c;  // C(k,2) * max(|gap|, max |sub|) (set-up)
   int32_t nqueue;   // tiles in the pruned queue
   int32_t redo;     // 1 when the first pruned pass missed its threshold
-  int32_t pad[42];
+  int64_t max_pause;  // longest pause seen inside a dependency wait (ticks of
+                      // the 100 MHz clock, see WaitClock); batched launches
+                      // report and clear it
+  int32_t pad[40];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte slot");
+
+// Time a dependency wait has spent waiting, for its watchdog.  The 100 MHz
+// wall clock is read at every check of the wait, and only gaps shorter than
+// kPauseTicks between two checks count: a running wave checks every few
+// microseconds, so a longer gap means the wave did not run (its queue was
+// preempted, for one), which is no sign of a missing dependency.  The longest
+// such gap is kept for the launch's report.
+constexpr int64_t kPauseTicks = 100000;  // 1 ms
+struct WaitClock {
+  int64_t last;
+  int64_t waited = 0;
+  int64_t pause = 0;
+  __device__ WaitClock() : last((int64_t)wall_clock64()) {}
+  // Takes a clock reading; returns the time waited so far (ticks).
+  __device__ int64_t tick() {
+    const int64_t now = (int64_t)wall_clock64();
+    const int64_t d = now - last;
+    last = now;
+    if (d < kPauseTicks)
+      waited += d;
+    else if (d > pause)
+      pause = d;
+    return waited;
+  }
+  __device__ void report(Ctrl *ctrl) const {
+    if (pause > 0)
+      __hip_atomic_fetch_max(&ctrl->max_pause, pause, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
 
 // Alignment mode bits (same values as MSA_END_GAPS_FREE / MSA_COOPTIMAL in
 // the C ABI).
@@ -140,13 +181,16 @@ constexpr int kSwSubMax = 32;      // largest alphabet (matrix kept in LDS)
 
 // Parameters of one batched launch, written into the launch's arena with its
 // inputs.  The launch sequence then takes only fixed arguments (this
-// descriptor's address, the control block, fixed grids), so it is captured
-// once per arena in a graph and replayed for every batch.
+// descriptor's address, the job descriptors' address, the control block,
+// fixed grids), so it is captured once per arena in a graph and replayed for
+// every batch.
 struct BatchArgs {
-  const JobDev *jobs;         // njobs descriptors
   const int64_t *jcols;       // njobs + 1: tile columns before job i
   int32_t *qjob, *qtile;      // the column queue: job index and first tile
   int32_t *flags;             // per-tile completion flags of all jobs
+  int32_t *gstatus;           // output: the launch-wide status at its end
+                              // ([0]) and the longest pause of a dependency
+                              // wait (int64 at [2], 100 MHz ticks)
   int64_t tiles;              // tiles of all jobs
   int64_t cols;               // columns of all jobs (queue length)
   int32_t njobs;

@@ -146,8 +146,9 @@ __device__ inline int64_t wall_now() { return (int64_t)wall_clock64(); }
 #define MSA_TRACE_POINT(jd, tile, j) do { } while (0)
 #endif
 
-// Watchdog for dependency waits: wall_clock64 runs at a fixed 100 MHz.
-constexpr int64_t kWaitLimitTicks = 200000000;  // 2 s
+// Watchdog for dependency waits: 2 s of waiting while the wave runs
+// (WaitClock: 100 MHz ticks, pauses of the queue excluded).
+constexpr int64_t kWaitLimitTicks = 200000000;
 // Longest pause between two polls of a dependency wait, in units of
 // s_sleep 2 (about 128 clocks each).
 #ifndef MSA_MAX_NAP
@@ -384,7 +385,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
         }
       }
     }
-    const int64_t t0 = wall_now();
+    WaitClock wc;
     int nap = 1;
     for (int it = 0;; ++it) {
       if (need) need = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch;
@@ -393,7 +394,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
         const int st = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (st == ST_EDEVICE) break;
-        if (wall_now() - t0 > kWaitLimitTicks) {
+        if (wc.tick() > kWaitLimitTicks) {
           atomicCAS(&ctrl->status, ST_OK, ST_EDEVICE);  // all lanes: idempotent
           break;
         }
@@ -401,6 +402,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
       for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(2);
       nap = nap < kMaxNap ? 2 * nap : kMaxNap;
     }
+    wc.report(ctrl);
   }
   __syncthreads();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -1292,9 +1294,10 @@ template <int K>
 static int launch_coopt_k(const JobDev &jd, Ctrl *ctrl, int32_t max_paths, uint8_t *aln_out,
                           int64_t *len_out, int32_t *npaths_out, hipStream_t s) {
   if constexpr (K <= 3) {
+    launch_begin();
     hipLaunchKernelGGL((coopt_kernel<K>), dim3(1), dim3(64), 0, s, jd, ctrl, max_paths, aln_out,
                        len_out, npaths_out);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+    return launch_end();
   } else {
     return -1;
   }
@@ -1532,9 +1535,10 @@ static int launch_nearopt_k(const JobDev &jd, Ctrl *ctrl, int64_t delta, int32_t
                             int64_t *scores_out, uint8_t *aln_out, int64_t *len_out,
                             int32_t *npaths_out, hipStream_t s) {
   if constexpr (K <= kNoMaxK) {
+    launch_begin();
     hipLaunchKernelGGL((nearopt_kernel<K>), dim3(1), dim3(64), 0, s, jd, ctrl, delta, max_paths,
                        scores_out, aln_out, len_out, npaths_out);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+    return launch_end();
   } else {
     return -1;
   }
@@ -1580,8 +1584,8 @@ __global__ void export_dirs_kernel(JobDev jd, const Ctrl *ctrl, uint8_t *out, in
 // rank among those columns in lexicographic order of (c_1..c_{k-1}).  Every
 // job's columns appear in the order of their first tile's wave, which makes
 // the queue a topological order of all dependencies.
-__global__ void batch_queue_kernel(const BatchArgs *__restrict__ a) {
-  const JobDev *__restrict__ jobs = a->jobs;
+__global__ void batch_queue_kernel(const BatchArgs *__restrict__ a,
+                                   const JobDev *__restrict__ jobs) {
   const int njobs = a->njobs;
   const int64_t *__restrict__ jcols = a->jcols;
   int32_t *qjob = a->qjob;
@@ -1650,11 +1654,16 @@ __device__ void batch_column(const JobDev &jd, int base, int epoch, Ctrl *ctrl, 
                            jd.jstatus, sm, hs, false, nullptr, false, false, c0 > 0, true);
 }
 
+// The job descriptors come as a kernel argument of their own (a fixed arena
+// offset, so the captured launch stays valid): read through a restrict
+// argument, the compiler proves that no store of the kernel reaches them and
+// keeps their fields in scalar registers; read through a pointer loaded from
+// the descriptor, every field would take vector registers.
 template <int KLO, int KHI, int NT>
 __global__ __launch_bounds__(NT) void batch_fill_kernel(const BatchArgs *__restrict__ a,
+                                                        const JobDev *__restrict__ jobs,
                                                         Ctrl *ctrl) {
   __shared__ alignas(16) char smraw[batch_smem_bytes<KLO, KHI>()];
-  const JobDev *__restrict__ jobs = a->jobs;
   const int32_t *__restrict__ qjob = a->qjob;
   const int32_t *__restrict__ qtile = a->qtile;
   const int32_t total = __builtin_amdgcn_readfirstlane((int32_t)a->cols);
@@ -1692,9 +1701,9 @@ __global__ __launch_bounds__(NT) void batch_fill_kernel(const BatchArgs *__restr
 // ...): walk, expand, write the outputs.
 template <int KLO, int KHI>
 __global__ __launch_bounds__(64) void batch_traceback_kernel(const BatchArgs *__restrict__ a,
+                                                             const JobDev *__restrict__ jobs,
                                                              Ctrl *ctrl) {
   __shared__ alignas(16) uint8_t dirb[4096];
-  const JobDev *__restrict__ jobs = a->jobs;
   const int njobs = __builtin_amdgcn_readfirstlane(a->njobs);
   const int gst = __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
@@ -1724,9 +1733,14 @@ __global__ void batch_zero_kernel(const BatchArgs *__restrict__ a) {
     flags[i] = 0;
 }
 
-// Readies the control block for the next launch on the same arena.
-__global__ void batch_finish_kernel(Ctrl *ctrl) {
+// Reports the launch-wide status (MSA_EDEVICE after a dependency wait timed
+// out) and the longest pause of a dependency wait, and readies the control
+// block for the next launch on the same arena.
+__global__ void batch_finish_kernel(const BatchArgs *__restrict__ a, Ctrl *ctrl) {
   if (threadIdx.x == 0) {
+    a->gstatus[0] = ctrl->status;
+    *reinterpret_cast<int64_t *>(a->gstatus + 2) = ctrl->max_pause;
+    ctrl->max_pause = 0;
     ctrl->head = 0;
     ctrl->status = ST_OK;
     ctrl->epoch = ctrl->epoch + 1;
@@ -1741,15 +1755,17 @@ constexpr int kFillThreads = 256;  // four waves per tile
 template <int K>
 static int launch_fill_k(const JobDev &jd, Ctrl *ctrl, const int32_t *order, int grid,
                          int pass, hipStream_t s) {
+  launch_begin();
   hipLaunchKernelGGL((fill_kernel<K, kFillThreads>), dim3(grid), dim3(kFillThreads), 0, s, jd,
                      ctrl, order, pass);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  return launch_end();
 }
 
 template <int K>
 static int launch_traceback_k(const JobDev &jd, Ctrl *ctrl, hipStream_t s) {
+  launch_begin();
   hipLaunchKernelGGL((traceback_kernel<K>), dim3(1), dim3(64), 0, s, jd, ctrl);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  return launch_end();
 }
 
 template <int K>
@@ -1767,9 +1783,10 @@ static int launch_export_k(const JobDev &jd, const Ctrl *ctrl, uint8_t *out, int
   int64_t blocks = (ncell + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
+  launch_begin();
   hipLaunchKernelGGL((export_dirs_kernel<K>), dim3((unsigned)blocks), dim3(256), 0, s, jd, ctrl,
                      out, ncell);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  return launch_end();
 }
 
 #define MSA_DISPATCH_K(k, fn, ...)                 \
@@ -1828,23 +1845,26 @@ constexpr int kBatchAuxGrid = 1024;
 constexpr int kBatchTraceGrid = 4096;
 
 template <int KLO, int KHI>
-static int launch_batch_k(const BatchArgs *d_args, Ctrl *ctrl, int grid, hipStream_t s) {
+static int launch_batch_k(const BatchArgs *d_args, const JobDev *d_jobs, Ctrl *ctrl, int grid,
+                          hipStream_t s) {
+  launch_begin();
   hipLaunchKernelGGL(batch_zero_kernel, dim3(kBatchAuxGrid), dim3(256), 0, s, d_args);
-  hipLaunchKernelGGL(batch_queue_kernel, dim3(kBatchAuxGrid), dim3(256), 0, s, d_args);
+  hipLaunchKernelGGL(batch_queue_kernel, dim3(kBatchAuxGrid), dim3(256), 0, s, d_args, d_jobs);
   hipLaunchKernelGGL((batch_fill_kernel<KLO, KHI, kBatchThreads>), dim3(grid),
-                     dim3(kBatchThreads), 0, s, d_args, ctrl);
+                     dim3(kBatchThreads), 0, s, d_args, d_jobs, ctrl);
   hipLaunchKernelGGL((batch_traceback_kernel<KLO, KHI>), dim3(kBatchTraceGrid), dim3(64), 0, s,
-                     d_args, ctrl);
-  hipLaunchKernelGGL(batch_finish_kernel, dim3(1), dim3(64), 0, s, ctrl);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+                     d_args, d_jobs, ctrl);
+  hipLaunchKernelGGL(batch_finish_kernel, dim3(1), dim3(64), 0, s, d_args, ctrl);
+  return launch_end();
 }
 
-int launch_batch(int kclass, const BatchArgs *d_args, Ctrl *ctrl, int grid, hipStream_t s) {
+int launch_batch(int kclass, const BatchArgs *d_args, const JobDev *d_jobs, Ctrl *ctrl, int grid,
+                 hipStream_t s) {
   switch (kclass) {
-    case 0: return launch_batch_k<2, 4>(d_args, ctrl, grid, s);
-    case 1: return launch_batch_k<5, 5>(d_args, ctrl, grid, s);
-    case 2: return launch_batch_k<6, 6>(d_args, ctrl, grid, s);
-    default: return launch_batch_k<7, 8>(d_args, ctrl, grid, s);
+    case 0: return launch_batch_k<2, 4>(d_args, d_jobs, ctrl, grid, s);
+    case 1: return launch_batch_k<5, 5>(d_args, d_jobs, ctrl, grid, s);
+    case 2: return launch_batch_k<6, 6>(d_args, d_jobs, ctrl, grid, s);
+    default: return launch_batch_k<7, 8>(d_args, d_jobs, ctrl, grid, s);
   }
 }
 

@@ -13,9 +13,13 @@ namespace msa {
 
 static int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
-// The batch descriptor sits right after the control block in every arena.
+// The batch descriptor sits right after the control block in every arena, and
+// the job descriptors right after it: both addresses are fixed per arena, so
+// a captured launch sequence stays valid for every batch the arena holds.
 constexpr int64_t kArgsOff = 256;
+constexpr int64_t kJobsOff = 512;
 static_assert(sizeof(Ctrl) <= kArgsOff, "control block first");
+static_assert(kArgsOff + (int64_t)sizeof(BatchArgs) <= kJobsOff, "descriptor before the jobs");
 
 int validate_job(const msa_job &j, int64_t) {
   if (j.k < 2 || j.k > MSA_MAX_K) return MSA_EINVAL;
@@ -72,7 +76,7 @@ int64_t Launch::overhead_bytes(int njobs, int64_t ntiles_total) {
     const int T = tile_edge_for_k(k);
     tables += a256((int64_t)ipow(T, k) * 4) + a256((int64_t)(k * (T - 1) + 2) * 4);
   }
-  return 512 + tables + a256((int64_t)njobs * sizeof(JobDev)) + a256((int64_t)(njobs + 1) * 8) +
+  return 768 + tables + a256((int64_t)njobs * sizeof(JobDev)) + a256((int64_t)(njobs + 1) * 8) +
          a256((int64_t)njobs * 24) + 3 * a256(ntiles_total * 4) + 255 * 255 * 4 + 4096;
 }
 
@@ -131,6 +135,7 @@ int Launch::ensure_graph(int kc, int grid) {
   bool ok = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
     const int rc = launch_batch(kc, reinterpret_cast<const BatchArgs *>(d_ + kArgsOff),
+                                reinterpret_cast<const JobDev *>(d_ + kJobsOff),
                                 reinterpret_cast<Ctrl *>(d_), grid, stream_);
     ok = hipStreamEndCapture(stream_, &g) == hipSuccess && rc == 0 && g;
   }
@@ -186,8 +191,8 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   int64_t o = 0;
   const int64_t off_ctrl = o;  o += 256;
   const int64_t off_args = o;  o = a256(o + (int64_t)sizeof(BatchArgs));
-  if (off_args != kArgsOff) return MSA_EINVAL;
   const int64_t off_jobs = o;  o = a256(o + (int64_t)nj * sizeof(JobDev));
+  if (off_args != kArgsOff || off_jobs != kJobsOff) return MSA_EINVAL;
   const int64_t off_jt = o;    o = a256(o + (int64_t)(nj + 1) * 8);
   const int64_t off_jc = o;    o = a256(o + (int64_t)(nj + 1) * 8);
   // substitution matrices, deduplicated by content
@@ -215,6 +220,7 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   const int64_t off_score = o;  o = a256(o + (int64_t)nj * 8);
   const int64_t off_len = o;    o = a256(o + (int64_t)nj * 8);
   const int64_t off_stat = o;   o = a256(o + (int64_t)nj * 4);
+  const int64_t off_gst = o;    o = a256(o + 16);
   std::vector<int64_t> job_out(nj);
   for (int i = 0; i < nj; ++i) {
     job_out[i] = o;
@@ -340,11 +346,11 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   // ---- batch descriptor (read by the launch sequence) ----
   BatchArgs args;
   memset(&args, 0, sizeof(args));
-  args.jobs = reinterpret_cast<const JobDev *>(d_ + off_jobs);
   args.jcols = reinterpret_cast<const int64_t *>(d_ + off_jc);
   args.qjob = reinterpret_cast<int32_t *>(d_ + off_qjob);
   args.qtile = reinterpret_cast<int32_t *>(d_ + off_qtile);
   args.flags = reinterpret_cast<int32_t *>(d_ + off_flags);
+  args.gstatus = reinterpret_cast<int32_t *>(d_ + off_gst);
   args.tiles = tiles;
   args.cols = jc[nj];
   args.njobs = nj;
@@ -364,6 +370,7 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
     ok = ok && hipGraphLaunch(graph_[kc], stream_) == hipSuccess;
   else
     ok = ok && launch_batch(kc, reinterpret_cast<const BatchArgs *>(d_ + off_args),
+                            reinterpret_cast<const JobDev *>(d_ + off_jobs),
                             reinterpret_cast<Ctrl *>(d_ + off_ctrl), grid, stream_) == 0;
   ok = ok && hipMemcpyAsync(h_out_, d_ + off_out, (size_t)out_bytes, hipMemcpyDeviceToHost,
                             stream_) == hipSuccess;
@@ -390,6 +397,18 @@ int Launch::wait() {
 bool Launch::interval_ms(hipEvent_t ref, float *t0, float *t1) const {
   return hipEventElapsedTime(t0, ref, start_) == hipSuccess &&
          hipEventElapsedTime(t1, ref, done_) == hipSuccess;
+}
+
+int32_t Launch::device_status() const {
+  const int nj = (int)meta_.size();
+  const int64_t off_gst = 2 * a256((int64_t)nj * 8) + a256((int64_t)nj * 4);
+  return *reinterpret_cast<const int32_t *>(h_out_ + off_gst);
+}
+
+int64_t Launch::device_max_pause_us() const {
+  const int nj = (int)meta_.size();
+  const int64_t off_gst = 2 * a256((int64_t)nj * 8) + a256((int64_t)nj * 4);
+  return *reinterpret_cast<const int64_t *>(h_out_ + off_gst + 8) / 100;  // 100 MHz ticks
 }
 
 void Launch::result(int i, LaunchResult *out) const {

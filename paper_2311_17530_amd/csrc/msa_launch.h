@@ -57,6 +57,15 @@ class Launch {
   // After ready()/wait(): result of the i-th staged job.
   void result(int i, LaunchResult *out) const;
   void fill_result(int i, msa_result *out) const;
+  // After ready()/wait(): the launch-wide device status (MSA_EDEVICE when a
+  // dependency wait of the fill timed out; a job's own status can also be
+  // MSA_EDEVICE when its traceback met inconsistent decisions).
+  int32_t device_status() const;
+  // After ready()/wait(): the longest pause (microseconds) a dependency wait
+  // of the fill saw between two of its checks, that is a time the fill did
+  // not run (its queue preempted); such pauses do not count towards the
+  // wait's time-out.  0 when there was none.
+  int64_t device_max_pause_us() const;
   int njobs() const { return (int)meta_.size(); }
   // After ready()/wait(): the launch's device interval (from its first copy
   // to its last) in milliseconds after `ref`, an event recorded earlier on

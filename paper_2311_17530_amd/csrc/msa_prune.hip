@@ -317,25 +317,28 @@ __global__ __launch_bounds__(64) void prune_check_kernel(PruneDev pd, Ctrl *ctrl
 }  // namespace
 
 int launch_prune_bounds(const PruneDev &pd, Ctrl *ctrl, hipStream_t s) {
+  launch_begin();
   hipLaunchKernelGGL(pair_table_kernel, dim3(2 * pd.npairs), dim3(64), 0, s, pd, ctrl);
   int pmax = 1;
   for (int q = 0; q < pd.npairs; ++q) pmax = max(pmax, pd.P[pd.pj[q]]);
   hipLaunchKernelGGL(pair_blockmax_kernel, dim3(pmax, pd.npairs), dim3(256), 0, s, pd, ctrl);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  return launch_end();
 }
 
 int launch_prune_select(const PruneDev &pd, Ctrl *ctrl, int pass, hipStream_t s) {
+  launch_begin();
   hipLaunchKernelGGL(prune_select_kernel, dim3(pd.nblocks), dim3(kSelBlock), 0, s, pd, ctrl,
                      pass);
   hipLaunchKernelGGL(prune_scan_kernel, dim3(1), dim3(kSelBlock), 0, s, pd, ctrl, pass);
   hipLaunchKernelGGL(prune_compact_kernel, dim3(pd.nblocks), dim3(kSelBlock), 0, s, pd, ctrl,
                      pass);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  return launch_end();
 }
 
 int launch_prune_check(const PruneDev &pd, Ctrl *ctrl, hipStream_t s) {
+  launch_begin();
   hipLaunchKernelGGL(prune_check_kernel, dim3(1), dim3(64), 0, s, pd, ctrl);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  return launch_end();
 }
 
 }  // namespace msa

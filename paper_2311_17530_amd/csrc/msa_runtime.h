@@ -27,7 +27,8 @@ int launch_prune_check(const PruneDev &pd, Ctrl *ctrl, hipStream_t s);
 // The batched launch sequence (flag clearing, queue, fill, traceback, control
 // block reset) for the batch described by d_args; grid workgroups for the
 // persistent fill.  Fixed arguments only, so it can be captured in a graph.
-int launch_batch(int kclass, const BatchArgs *d_args, Ctrl *ctrl, int grid, hipStream_t s);
+int launch_batch(int kclass, const BatchArgs *d_args, const JobDev *d_jobs, Ctrl *ctrl, int grid,
+                 hipStream_t s);
 int batch_occupancy(int kclass);
 // streaming k = 3 fill (msa_sweep3.hip), for plans with sweep3_eligible
 int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, hipStream_t s);

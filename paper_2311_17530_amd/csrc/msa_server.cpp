@@ -80,6 +80,9 @@ struct msa_server {
   // jobs that ended with a status other than MSA_OK, and the last such status
   int64_t n_failed = 0;
   int32_t last_failure = MSA_OK;
+  // longest pause a launch's fill saw inside a dependency wait (its queue
+  // not running), microseconds
+  int64_t max_pause_us = 0;
   std::vector<std::pair<float, float>> intervals;
 
   void run();
@@ -159,12 +162,16 @@ void msa_server::collect(Slot &s) {
   if (ref && s.launch->interval_ms(ref, &t0, &t1)) intervals.emplace_back(t0, t1);
   ++n_launches;
   n_jobs += (int64_t)s.tickets.size();
+  max_pause_us = std::max(max_pause_us, s.launch->device_max_pause_us());
   for (size_t i = 0; i < s.tickets.size(); ++i) {
     LaunchResult r;
     s.launch->result((int)i, &r);
     Done &d = done[s.tickets[i]];
     d.status = r.status;
-    if (r.status != MSA_OK) note_failure(r.status, 1, "launch result");
+    if (r.status != MSA_OK)
+      note_failure(r.status, 1,
+                   s.launch->device_status() != MSA_OK ? "launch result: dependency wait timed out"
+                                                       : "launch result: job status");
     d.score = r.score;
     d.aln_len = r.aln_len;
     d.k = r.k;
@@ -346,10 +353,11 @@ extern "C" int msa_server_stats(msa_server *srv, int64_t *out, int32_t n) {
     last = std::max(last, (double)x.second);
   }
   if (open) busy += hi - lo;
-  const int64_t v[7] = {srv->n_launches, srv->n_jobs, (int64_t)(busy * 1000.0),
+  const int64_t v[8] = {srv->n_launches, srv->n_jobs, (int64_t)(busy * 1000.0),
                         open ? (int64_t)((last - first) * 1000.0) : 0,
-                        (int64_t)srv->queue.size(), srv->n_failed, srv->last_failure};
-  for (int i = 0; i < n && i < 7; ++i) out[i] = v[i];
+                        (int64_t)srv->queue.size(), srv->n_failed, srv->last_failure,
+                        srv->max_pause_us};
+  for (int i = 0; i < n && i < 8; ++i) out[i] = v[i];
   return MSA_OK;
 }
 

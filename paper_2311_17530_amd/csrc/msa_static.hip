@@ -164,6 +164,7 @@ extern "C" int msa_dp_align_static(const uint8_t *d_seqs, const int32_t *lens, i
   JobDev jd;
   fill_jobdev(p, ws, alpha, gap, &jd);
   hipStream_t s = (hipStream_t)hip_stream;
+  launch_begin();
   hipLaunchKernelGGL(static_setup_kernel, dim3(1), dim3(256), 0, s, jd,
                      reinterpret_cast<Ctrl *>(ws + p.off_ctrl),
                      reinterpret_cast<uint8_t *>(ws + p.off_sub),
@@ -174,6 +175,6 @@ extern "C" int msa_dp_align_static(const uint8_t *d_seqs, const int32_t *lens, i
     hipLaunchKernelGGL(static_zero_kernel, dim3((unsigned)std::min<int64_t>(1024, words / 256 + 1)),
                        dim3(256), 0, s, reinterpret_cast<int32_t *>(ws + p.off_x0), words);
   }
-  if (hipGetLastError() != hipSuccess) return MSA_EDEVICE;
+  if (launch_end() != 0) return MSA_EDEVICE;
   return run_plain_set_up(p, ws, alpha, d_seqs, d_score, d_aln, aln_cap, d_aln_len, d_status, s);
 }

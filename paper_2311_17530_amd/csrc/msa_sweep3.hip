@@ -59,7 +59,7 @@ constexpr int kSwSeqPad = 128;    // LDS bytes around the third sequence
 constexpr int kSwThreads = (kSwNW + 1) * 64;
 constexpr int kSwT = 16;          // tile edge of the direction blocks (k = 3)
 constexpr int kSwDbs = kSwT * kSwT * kSwT;
-constexpr int64_t kSwWaitTicks = 200000000;  // 2 s of the 100 MHz clock
+constexpr int64_t kSwWaitTicks = 200000000;  // 2 s of waiting (WaitClock ticks)
 
 static_assert(kSwDbs == 4096, "direction blocks of edge 16");
 static_assert(tile_edge_for_k(3) == kSwT, "same blocks as the tile kernel");
@@ -200,10 +200,12 @@ struct SwLoader {
   }
 
   // Slow path: reloads the values (into registers of its own) until every
-  // one carries this launch's tag or the watchdog fires.
+  // one carries this launch's tag or the watchdog fires (WaitClock: pauses of
+  // the queue do not count as waiting).
   __device__ __forceinline__ void respin(const int32_t (&a)[2], int32_t (&v)[2], int tag,
-                                         Ctrl *ctrl, int64_t t0) const {
+                                         Ctrl *ctrl) const {
     int32_t u[2];
+    WaitClock wc;
     for (int it = 0;; ++it) {
       __builtin_amdgcn_s_sleep(1);
 #pragma unroll
@@ -213,12 +215,13 @@ struct SwLoader {
         const int st = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (st == -4) break;  // another workgroup timed out: stop waiting
-        if ((int64_t)wall_clock64() - t0 > kSwWaitTicks) {
+        if (wc.tick() > kSwWaitTicks) {
           atomicCAS(&ctrl->status, 0, -4);
           break;
         }
       }
     }
+    wc.report(ctrl);
     v[0] = u[0];
     v[1] = u[1];
   }
@@ -227,12 +230,12 @@ struct SwLoader {
   // (reloaded while any carries another launch's tag), to LDS.  The first
   // check is straight-line code, so its wait counts only the younger loads.
   __device__ __forceinline__ void finish(int s, int back, int32_t (&v)[2], int tag, SwSmem &sm,
-                                         int lane, Ctrl *ctrl, int64_t t0, int &nspin) const {
+                                         int lane, Ctrl *ctrl, int &nspin) const {
     int32_t a[2];
 #pragma unroll
     for (int x = 0; x < 2; ++x) a[x] = acc[x] - (back == kSwPf ? lag[x] : back * linc[x]);
     if (stale(a, v, tag)) {
-      respin(a, v, tag, ctrl, t0);
+      respin(a, v, tag, ctrl);
       ++nspin;
     }
     const bool r0 = (unsigned)a[0] <= (unsigned)ohi[0];
@@ -407,7 +410,9 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
     const bool cblock = B0 == sd.n0 / kSwNW && B1 == sd.n1 / kSwLanes;
     const int wc = sd.n0 % kSwNW, jc = sd.n1 % kSwLanes;
     const int sc = sd.n2 + jc + wc;
+#ifdef MSA_TRACE
     const int64_t t0 = (int64_t)wall_clock64();
+#endif
     int nspin = 0;
     {
       // the halo of steps -1 (rows -2 / -1's lane -1) and 0, then steps 1 ..
@@ -415,8 +420,8 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
       int32_t a[2], b[2];
       ld.issue(a);
       ld.issue(b);
-      ld.finish(-2, 2, a, tag, sm, j, ctrl, t0, nspin);
-      ld.finish(-1, 1, b, tag, sm, j, ctrl, t0, nspin);
+      ld.finish(-2, 2, a, tag, sm, j, ctrl, nspin);
+      ld.finish(-1, 1, b, tag, sm, j, ctrl, nspin);
     }
     int32_t q[kSwPf][2];
 #pragma unroll
@@ -430,7 +435,7 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
       for (int i = 0; i < kSwUnroll; ++i) {
         const int s = s0 + i;
         // during step s: step s + 1's halo (loaded kSwPf steps ago)
-        ld.finish(s, kSwPf, q[i % kSwPf], tag, sm, j, ctrl, t0, nspin);
+        ld.finish(s, kSwPf, q[i % kSwPf], tag, sm, j, ctrl, nspin);
         if (cblock && s == sc + 1)
           *sd.score_out = (int64_t)(sm.ring[sc & (kSwRing - 1)][wc][jc + 1] >> 3);
         sw_barrier();
@@ -515,8 +520,9 @@ int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, hipStre
     if (want > sizeof(SwSmem) && want <= (size_t)lds_wg) pad = want - sizeof(SwSmem);
   }
   const int grid = p.sw_nb0 * p.sw_nb1;
+  launch_begin();
   hipLaunchKernelGGL(sweep3_kernel, dim3(grid), dim3(kSwThreads), pad, s, sd, ctrl);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  return launch_end();
 }
 
 }  // namespace msa
