@@ -35,13 +35,18 @@ struct JobDev {
   int32_t n[kMaxK];            // sequence lengths
   int32_t P[kMaxK];            // tiles per dimension (incl. the v_i = 0 layer)
   int32_t tstride[kMaxK];      // row-major tile strides (last dim fastest)
+  // division by tstride[i] as a multiply-high (see udiv_magic, msa_plan.cpp):
+  // multiplier, and the two shifts in the low and the next byte
+  uint32_t tdm[kMaxK];
+  uint32_t tdsh[kMaxK];
   int32_t ntiles;
   int32_t nwaves;              // sum(P) - k + 1
   int32_t dbs;                 // direction block stride (T^k rounded to 16)
   int32_t seq_off[kMaxK];      // offsets of each sequence in the seq buffer
   int64_t face_off[kMaxK];     // element offset of face array i in `faces`
   int64_t fplane[kMaxK];       // elements per face plane of dimension i
-  int64_t fstride[kMaxK][kMaxK];  // face-plane strides: fstride[i][j], j != i
+  uint32_t fbstride[kMaxK][kMaxK];  // face-plane strides in bytes: fbstride[i][j],
+                                    // j != i (below 2^32, checked by the plan)
   int64_t total_len;           // sum of lengths (traceback path capacity)
   // device pointers (filled per call for the plain path)
   const uint8_t *seqs;         // concatenated sequences

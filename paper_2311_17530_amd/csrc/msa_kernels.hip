@@ -168,6 +168,24 @@ __device__ inline void face_store(int32_t *p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Tile coordinates of a (wave-uniform) row-major tile index: the digits in
+// the mixed radix P, one division by tstride[i] per dimension, each a
+// multiply-high with the job's constants (tdm, tdsh; exact for every 32-bit
+// index), so they take scalar instructions.
+template <int K>
+__device__ __forceinline__ void tile_coords(const JobDev &jd, int tile, int (&c)[K]) {
+  uint32_t rem = (uint32_t)tile;
+#pragma unroll
+  for (int i = 0; i < K - 1; ++i) {
+    const uint32_t t = __umulhi(jd.tdm[i], rem);
+    const uint32_t sh = jd.tdsh[i];
+    const uint32_t q = (t + ((rem - t) >> (sh & 0xffu))) >> (sh >> 8);
+    c[i] = (int)q;
+    rem -= q * (uint32_t)jd.tstride[i];
+  }
+  c[K - 1] = (int)rem;
+}
+
 // Per-launch constant table into LDS (done once per persistent workgroup).
 template <int K, int NT>
 __device__ void load_tables(const JobDev &jd, int alpha, Smem<K> &sm) {
@@ -260,9 +278,9 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
 
   int c[K], lo[K], ext[K];
   bool origin = true, corner = true, lowtile = false, fartile = false;
+  tile_coords<K>(jd, tile, c);
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    c[i] = (tile / jd.tstride[i]) % jd.P[i];
     lo[i] = c[i] == 0 ? 0 : (c[i] - 1) * T + 1;
     ext[i] = c[i] == 0 ? 1 : min(T, jd.n[i] - (c[i] - 1) * T);
     origin = origin && c[i] == 0;
@@ -442,15 +460,24 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
 #pragma unroll
         for (int di = 0; di < DG; ++di) {
           const int i = i0 + di;
-          const int32_t *plane =
-              c[i] > 0 ? jd.faces + jd.face_off[i] + (int64_t)(c[i] - 1) * jd.fplane[i]
-                       : jd.faces;
+          // Byte address of the halo's first cell (v_j = lo_j - 1, j != i)
+          // in the face plane of tile c - e_i: wave-uniform, in scalar
+          // registers.  A slot adds sum_j l_j * fbstride[i][j] with 32 x 32 ->
+          // 64-bit multiply-adds (digits l_j <= T, byte strides below 2^32).
+          int64_t hb = 0;
+          if (c[i] > 0) {
+            hb = jd.face_off[i] + (int64_t)(c[i] - 1) * jd.fplane[i];
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+              if (j != i) hb += (int64_t)(lo[j] - 1) * (jd.fbstride[i][j] >> 2);
+          }
+          const uint64_t hbase = (uint64_t)jd.faces + 4 * (uint64_t)hb;
 #pragma unroll
           for (int it = 0; it < CH; ++it) {
             const uint32_t w = slot(it0 + it);
             int s = 0, q = 0;
             bool valid = (w >> 31) == 0, neg = (c[i] == 0);
-            int64_t foff = 0;
+            uint64_t addr = hbase;
             int src = 1 << i;  // the cell lies in tile c - e_src
 #pragma unroll
             for (int j = K - 1; j >= 0; --j) {
@@ -458,17 +485,17 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
               const int l = HS::digit(w, q++);
               valid = valid && l <= ext[j];
               s += l * C::sstride(j);
-              const int v = lo[j] - 1 + l;
-              neg = neg || v < 0;
+              neg = neg || lo[j] - 1 + l < 0;
               src |= (l == 0 ? 1 : 0) << j;
-              foff += (int64_t)v * jd.fstride[i][j];
+              addr += (uint64_t)(uint32_t)l * jd.fbstride[i][j];
             }
             valid = valid && !(own0 && i == 0);  // copied inside LDS above
             sidx[di][it] = valid ? s : -1;
             // a cell of a pruned tile was never computed: -infinity
             const bool take = valid && !neg && ((kbits >> (src & 63)) & 1) != 0;
             // unconditional load from a clamped in-range offset, then select
-            const int32_t got = face_load(plane + (take ? foff : 0));
+            const int32_t got =
+                face_load(take ? reinterpret_cast<const int32_t *>(addr) : jd.faces);
             val[di][it] = take ? got : kNegKey;
           }
         }
@@ -728,19 +755,26 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     constexpr int DG = K * IT <= 32 ? K : 1;  // dimensions per pass
     for (int i0 = 0; i0 < K; i0 += DG) {
       int32_t val[DG][IT];
-      int64_t fo[DG][IT];
+      uint64_t fo[DG][IT];  // byte addresses
       bool st[DG][IT];
 #pragma unroll
       for (int di = 0; di < DG; ++di) {
         const int i = i0 + di;
         const bool has_succ = c[i] < jd.P[i] - 1 && !(cols && i == 0);
+        // byte address of the face's first cell (v_j = lo_j) in plane c_i:
+        // wave-uniform, as in the halo load
+        int64_t eb = jd.face_off[i] + (int64_t)c[i] * jd.fplane[i];
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+          if (j != i) eb += (int64_t)lo[j] * (jd.fbstride[i][j] >> 2);
+        const uint64_t ebase = (uint64_t)jd.faces + 4 * (uint64_t)eb;
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
           const int idx = tid + it * NT;
           int rem = idx;
           int sidx = ext[i] * C::sstride(i);
           bool valid = has_succ && idx < cnt;
-          int64_t foff = 0;
+          uint64_t addr = ebase;
 #pragma unroll
           for (int j = K - 1; j >= 0; --j) {
             if (j == i) continue;
@@ -748,10 +782,10 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
             rem /= T;
             valid = valid && qq < ext[j];
             sidx += (qq + 1) * C::sstride(j);
-            foff += (int64_t)(lo[j] + qq) * jd.fstride[i][j];
+            addr += (uint64_t)(uint32_t)qq * jd.fbstride[i][j];
           }
           val[di][it] = sm.S[valid ? sidx : 0];
-          fo[di][it] = jd.face_off[i] + (int64_t)c[i] * jd.fplane[i] + foff;
+          fo[di][it] = addr;
           st[di][it] = valid;
         }
       }
@@ -759,7 +793,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
       for (int di = 0; di < DG; ++di)
 #pragma unroll
         for (int it = 0; it < IT; ++it)
-          if (st[di][it]) face_store(jd.faces + fo[di][it], val[di][it]);
+          if (st[di][it]) face_store(reinterpret_cast<int32_t *>(fo[di][it]), val[di][it]);
     }
   }
 
@@ -840,7 +874,32 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
 #endif
 }
 
-// Plain path: one job, descriptor passed by value.
+// The plain fill's job descriptor for one tile: the kernel's first argument,
+// read in the kernel-argument segment (explicit arguments start at its
+// offset 0).  The descriptor's fields are loop-invariant, so the compiler
+// would load them all before the persistent loop and, short of scalar
+// registers, park them in vector register lanes, paying a v_readlane (a
+// vector instruction) at every use in every tile.  Seen through a pointer
+// into the segment (constant address space) that is opaque at each tile,
+// they are reloaded per tile with scalar loads instead; the segment stays in
+// the scalar cache.  (The parameter's own address would not do: taking it
+// makes the compiler copy the argument to private memory.)  k = 8, whose
+// tile code takes every vector register anyway, keeps the parameter: there
+// the per-tile reloads made the compiler spill to scratch.
+template <int K>
+__device__ __forceinline__ const JobDev &job_arg(const JobDev &jd) {
+  if constexpr (K >= 8) {
+    return jd;
+  } else {
+    using CJob = const __attribute__((address_space(4))) JobDev;
+    CJob *kp = (CJob *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(kp));
+    return *(const JobDev *)kp;
+  }
+}
+
+// Plain path: one job, descriptor passed by value (first argument: job_arg
+// reads it in place).
 // pass (pruned mode): 1 = first pass, 2 = second pass, which runs only when
 // the first missed its threshold; 0 otherwise.
 template <int K, int NT>
@@ -882,13 +941,13 @@ __global__ __launch_bounds__(NT) void fill_kernel(JobDev jd, Ctrl *ctrl,
     if (cols) {
       const int base = __builtin_amdgcn_readfirstlane(jd.corder[qi]);
       for (int c0 = 0; c0 < jd.P[0]; ++c0)
-        process_tile<K, NT>(jd, alpha, gap, base + c0 * jd.tstride[0], epoch, ctrl,
-                                  &ctrl->status, sm, hs, egf, &ctrl->best, coopt, false,
-                                  c0 > 0, true, nearopt);
+        process_tile<K, NT>(job_arg<K>(jd), alpha, gap, base + c0 * jd.tstride[0], epoch, ctrl,
+                            &ctrl->status, sm, hs, egf, &ctrl->best, coopt, false, c0 > 0, true,
+                            nearopt);
     } else {
-      process_tile<K, NT>(jd, alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]),
-                                epoch, ctrl, &ctrl->status, sm, hs, egf, &ctrl->best, coopt,
-                                prune, false, false, nearopt);
+      process_tile<K, NT>(job_arg<K>(jd), alpha, gap, __builtin_amdgcn_readfirstlane(order[qi]),
+                          epoch, ctrl, &ctrl->status, sm, hs, egf, &ctrl->best, coopt, prune,
+                          false, false, nearopt);
     }
   }
 }
@@ -1651,7 +1710,7 @@ __device__ void batch_column(const JobDev &jd, int base, int epoch, Ctrl *ctrl, 
   const HaloSlots<K, NT> hs(threadIdx.x);
   for (int c0 = 0; c0 < jd.P[0]; ++c0)
     process_tile<K, NT>(jd, jd.alpha, jd.gap, base + c0 * jd.tstride[0], epoch, ctrl,
-                           jd.jstatus, sm, hs, false, nullptr, false, false, c0 > 0, true);
+                        jd.jstatus, sm, hs, false, nullptr, false, false, c0 > 0, true);
 }
 
 // The job descriptors come as a kernel argument of their own (a fixed arena

@@ -66,6 +66,9 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
     int64_t plane = 1;
     for (int j = k - 1; j >= 0; --j) {
       if (j == i) continue;
+      // the kernels form face addresses from 32-bit byte strides (a stride
+      // of 2^30 words needs a face plane of at least 2^31 words, 8 GiB)
+      if (plane >= ((int64_t)1 << 30)) return MSA_ENOMEM;
       q.fstride[i][j] = plane;
       if (!mul_ok(plane, (int64_t)q.n[j] + 1, lim)) return MSA_ENOMEM;
       plane *= (int64_t)q.n[j] + 1;
@@ -232,6 +235,24 @@ int check_scoring_mode(const int32_t *lens, int32_t k, const int8_t *submat, int
 
 int64_t nearopt_bytes(const Plan &p) { return align256(p.ntiles * (int64_t)p.dbs * 4); }
 
+// Unsigned division of any 32-bit n by an invariant d >= 1 as
+// q = (t + ((n - t) >> s1)) >> s2 with t = mulhi(m, n), after Granlund and
+// Montgomery, "Division by invariant integers using multiplication" (1994):
+// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1),
+// s2 = max(l - 1, 0).  The kernels use it for tile coordinates, which then
+// take scalar instructions instead of a division on the vector unit.
+void udiv_magic(uint32_t d, uint32_t *m, uint32_t *sh) {
+  int l = 0;
+  while (l < 32 && ((uint64_t)1 << l) < d) ++l;
+  *m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1);
+  *sh = (uint32_t)std::min(l, 1) | ((uint32_t)std::max(l - 1, 0) << 8);
+}
+
+uint32_t udiv_apply(uint32_t n, uint32_t m, uint32_t sh) {
+  const uint32_t t = (uint32_t)(((uint64_t)m * n) >> 32);
+  return (t + ((n - t) >> (sh & 0xff))) >> (sh >> 8);
+}
+
 void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd) {
   memset(jd, 0, sizeof(*jd));
   jd->k = p.k;
@@ -243,11 +264,12 @@ void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd) {
     jd->n[i] = p.n[i];
     jd->P[i] = p.P[i];
     jd->tstride[i] = p.tstride[i];
+    udiv_magic((uint32_t)p.tstride[i], &jd->tdm[i], &jd->tdsh[i]);
     jd->seq_off[i] = off;
     off += p.n[i];
     jd->face_off[i] = p.face_off[i];
     jd->fplane[i] = p.fplane[i];
-    for (int j = 0; j < p.k; ++j) jd->fstride[i][j] = p.fstride[i][j];
+    for (int j = 0; j < p.k; ++j) jd->fbstride[i][j] = (uint32_t)(4 * p.fstride[i][j]);
   }
   jd->ntiles = (int32_t)p.ntiles;
   jd->nwaves = p.nwaves;

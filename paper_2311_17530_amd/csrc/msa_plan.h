@@ -80,6 +80,10 @@ int check_scoring_mode(const int32_t *lens, int32_t k, const int8_t *submat, int
 // layout (at offset p.bytes), one int32 per cell laid out as the direction
 // blocks.
 int64_t nearopt_bytes(const Plan &p);
+// Division by an invariant (tile strides): multiplier and shifts, and the
+// quotient they give (the kernels' formula, for host checks).
+void udiv_magic(uint32_t d, uint32_t *m, uint32_t *sh);
+uint32_t udiv_apply(uint32_t n, uint32_t m, uint32_t sh);
 
 // Device descriptor for a plan placed at workspace base `ws`.
 void fill_jobdev(const Plan &p, char *ws, int alpha, int gap, JobDev *jd);
