@@ -129,7 +129,10 @@ template <int K>
 struct Smem {
   int32_t S[Cfg<K>::NS];                                // tile keys with halo
   int32_t PT[Cfg<K>::NP * Cfg<K>::T * Cfg<K>::T];       // pair scores << k
-  int32_t SUB[kSubLds * kSubLds];                       // substitution matrix << k
+  // substitution matrix << k: |sub| <= 127, so the values fit 16 bits for
+  // every k <= 8 (the 2 KB saved let one more k = 3 or k = 4 tile
+  // workgroup share a compute unit's LDS)
+  int16_t SUB[kSubLds * kSubLds];
   uint8_t RES[K * Cfg<K>::T];                           // residues of the tile
   uint16_t LORD[K <= 3 ? 1 : Cfg<K>::L];                // LineOrder<K> (k >= 4)
   alignas(16) uint8_t DIRB[Cfg<K>::REGDIR ? 16 : Cfg<K>::DBS];  // staged direction bytes
@@ -138,7 +141,9 @@ struct Smem {
 __device__ inline int64_t wall_now() { return (int64_t)wall_clock64(); }
 
 // Optional phase timestamps per tile (compile with -DMSA_TRACE): 8 int64 per
-// tile, written by every lane of the wave (same value, no divergent branch).
+// tile, written by every lane of the wave (same value, no divergent branch):
+// 0 start, 1 dependencies met, 2 halo loaded, 3 swept, 5 faces exported,
+// 6 flag stored, 4 end (direction block stored), 7 the workgroup.
 #ifdef MSA_TRACE
 #define MSA_TRACE_POINT(jd, tile, j) \
   do { if ((jd).trace) (jd).trace[(int64_t)(tile) * 8 + (j)] = wall_now(); } while (0)
@@ -192,7 +197,7 @@ __device__ void load_tables(const JobDev &jd, int alpha, Smem<K> &sm) {
   const int tid = threadIdx.x;
   if (alpha <= kSubLds)
     for (int e = tid; e < alpha * alpha; e += NT)
-      sm.SUB[(e / alpha) * kSubLds + e % alpha] = ((int32_t)jd.sub[e]) * (1 << K);
+      sm.SUB[(e / alpha) * kSubLds + e % alpha] = (int16_t)(((int32_t)jd.sub[e]) * (1 << K));
   if constexpr (K >= 4)
     for (int p = tid; p < Cfg<K>::L; p += NT) sm.LORD[p] = kLineOrder<K>.v[p];
 }
@@ -329,7 +334,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
       for (int idx = tid; idx < TT; idx += NT) {
         const int a = sm.RES[i * T + idx / T];
         const int b = sm.RES[j * T + idx % T];
-        pt[idx] = alpha <= kSubLds ? sm.SUB[a * kSubLds + b]
+        pt[idx] = alpha <= kSubLds ? (int32_t)sm.SUB[a * kSubLds + b]
                                    : ((int32_t)jd.sub[a * alpha + b]) * (1 << K);
       }
     }
@@ -869,6 +874,7 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
     }
   }
 
+  MSA_TRACE_POINT(jd, tile, 4);
 #ifdef MSA_TRACE
   if (jd.trace) jd.trace[(int64_t)tile * 8 + 7] = blockIdx.x;
 #endif
@@ -1718,8 +1724,15 @@ __device__ void batch_column(const JobDev &jd, int base, int epoch, Ctrl *ctrl, 
 // argument, the compiler proves that no store of the kernel reaches them and
 // keeps their fields in scalar registers; read through a pointer loaded from
 // the descriptor, every field would take vector registers.
+// Waves per SIMD the batched fill is compiled for: as many workgroups as the
+// k class's LDS allows (k = 2..4 and 5: five; k = 6: four; k = 7..8: one).
+constexpr int batch_waves_per_eu(int klo, int khi) {
+  return khi <= 5 ? 5 : khi == 6 ? 4 : 1;
+}
+
 template <int KLO, int KHI, int NT>
-__global__ __launch_bounds__(NT) void batch_fill_kernel(const BatchArgs *__restrict__ a,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu(KLO, KHI))))
+void batch_fill_kernel(const BatchArgs *__restrict__ a,
                                                         const JobDev *__restrict__ jobs,
                                                         Ctrl *ctrl) {
   __shared__ alignas(16) char smraw[batch_smem_bytes<KLO, KHI>()];

@@ -6,6 +6,8 @@ busy, so their throughput scales with occupancy.  A change that moves the job
 descriptor fields from scalar to vector registers (for instance reading them
 through a pointer the compiler cannot prove unwritten) costs a third or more
 of the batched throughput without changing any result; this test fails on it.
+So does any use of scratch memory (register spills, or a private copy of the
+descriptor, which taking a by-value kernel argument's address produces).
 """
 import re
 import subprocess
@@ -18,10 +20,11 @@ from paper_2311_17530_amd import build as B
 # (the compiler's figure, limited by registers and by the LDS a workgroup
 # declares)
 FLOORS = {
-    "msa::fill_kernel<3, 256>": 5,
-    "msa::fill_kernel<4, 256>": 4,
+    "msa::fill_kernel<3, 256>": 6,
+    "msa::fill_kernel<4, 256>": 5,
     "msa::fill_kernel<5, 256>": 5,
-    "msa::batch_fill_kernel<2, 4, 256>": 4,
+    "msa::fill_kernel<6, 256>": 4,
+    "msa::batch_fill_kernel<2, 4, 256>": 5,
     "msa::batch_fill_kernel<5, 5, 256>": 5,
     "msa::batch_fill_kernel<6, 6, 256>": 4,
 }
@@ -40,11 +43,15 @@ def usage():
            "-c", str(src), "-o", "/dev/null"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
-    names, vgprs, occ = [], [], []
+    names, vgprs, occ, scratch = [], [], [], []
     for line in r.stderr.splitlines():
         m = re.search(r"remark: Function Name: (\S+)", line)
         if m:
             names.append(m.group(1))
+            continue
+        m = re.search(r"remark:\s+ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m:
+            scratch.append(int(m.group(1)))
             continue
         m = re.search(r"remark:\s+VGPRs: (\d+)", line)
         if m:
@@ -53,13 +60,19 @@ def usage():
         m = re.search(r"remark:\s+Occupancy \[waves/SIMD\]: (\d+)", line)
         if m:
             occ.append(int(m.group(1)))
-    assert len(names) == len(vgprs) == len(occ) and names
-    return {d: (v, o) for d, v, o in zip(_demangle(names), vgprs, occ)}
+    assert len(names) == len(vgprs) == len(occ) == len(scratch) and names
+    return {d: (v, o, sc) for d, v, o, sc in zip(_demangle(names), vgprs, occ, scratch)}
 
 
 @pytest.mark.parametrize("kernel", sorted(FLOORS))
 def test_fill_kernel_occupancy(usage, kernel):
     hits = [(d, vo) for d, vo in usage.items() if d.startswith("void " + kernel + "(")]
     assert len(hits) == 1, (kernel, [d for d in usage if "fill_kernel" in d])
-    d, (v, o) = hits[0]
+    d, (v, o, sc) = hits[0]
     assert o >= FLOORS[kernel], f"{d}: {v} VGPRs, {o} waves/SIMD < {FLOORS[kernel]}"
+    assert sc == 0, f"{d}: {sc} bytes of scratch per lane"
+
+
+def test_no_kernel_uses_scratch(usage):
+    used = {d: sc for d, (v, o, sc) in usage.items() if sc}
+    assert not used, used
