@@ -131,8 +131,10 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
   return MSA_OK;
 }
 
+// The streaming k = 3 fill covers the plain and the end-gap-free modes.
 bool sweep3_eligible(const Plan &p, int alpha, int32_t flags) {
-  return p.k == 3 && flags == 0 && alpha >= 1 && alpha <= kSwSubMax && p.n[2] <= kSwSeqMax;
+  return p.k == 3 && (flags & ~kEndGapsFree) == 0 && alpha >= 1 && alpha <= kSwSubMax &&
+         p.n[2] <= kSwSeqMax;
 }
 
 void make_tile_order(const Plan &p, std::vector<int32_t> *order) {

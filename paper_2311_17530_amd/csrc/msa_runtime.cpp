@@ -158,7 +158,7 @@ static int run_fill(const Plan &p, char *ws, JobDev &jd, hipStream_t s, int alph
   TuneChoice tc;
   tune_get(kTunePlain, p.k, length_bucket(p.n, p.k), &tc);
   if (tc.variant != 2 && sweep3_eligible(p, alpha, workspace_flags(ws)))
-    return launch_sweep3(p, ws, jd, ctrl, s);
+    return launch_sweep3(p, ws, jd, ctrl, workspace_flags(ws), s);
   const int32_t *order = reinterpret_cast<const int32_t *>(ws + p.off_order);
   int grid = fill_grid(p, tc.variant == 2 ? tc.wpc : 0);
   if (jd.ncols > 0 && grid > jd.ncols) grid = jd.ncols;

@@ -31,7 +31,8 @@ int launch_batch(int kclass, const BatchArgs *d_args, const JobDev *d_jobs, Ctrl
                  hipStream_t s);
 int batch_occupancy(int kclass);
 // streaming k = 3 fill (msa_sweep3.hip), for plans with sweep3_eligible
-int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, hipStream_t s);
+int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, int32_t flags,
+                  hipStream_t s);
 
 // runtime (msa_runtime.cpp)
 int device_cu_count();

@@ -78,6 +78,9 @@ struct Sweep3Dev {
   int32_t ts0, ts1;           // tile strides of dimensions 0 and 1 (dimension 2: 1)
   int64_t *score_out;
   int64_t *trace;             // debug builds: 8 words per workgroup ticket
+  int32_t egf;                // end-gap-free mode
+  int64_t *best;              // end-gap-free: max of (score << 32 | row-major
+                              // cell index) over the far faces
 };
 
 struct SwSmem {
@@ -125,7 +128,10 @@ struct SwLoader {
   int32_t acc[2], linc[2], ohi[2], lag[2];  // ohi = span * linc, lag = kSwPf * linc
   int32_t dst1[kSwRing];  // LDS word index (in the ring array) of element 1, per slot s % 4
 
-  __device__ void set(int x, const int32_t *base, int llo, int inc, int span, int s_first) {
+  // (set-up code is force-inlined as well: a call would need the kernel's
+  // by-value descriptor in memory, a copy to scratch)
+  __device__ __forceinline__ void set(int x, const int32_t *base, int llo, int inc, int span,
+                                      int s_first) {
     wbase[x] = base;
     linc[x] = inc;
     acc[x] = (s_first - llo) * inc;
@@ -133,8 +139,8 @@ struct SwLoader {
     lag[x] = kSwPf * inc;
   }
 
-  __device__ SwLoader(const Sweep3Dev &sd, SwSmem &sm, int B0, int B1, int lane,
-                      const int32_t *dummy, int s_first) {
+  __device__ __forceinline__ SwLoader(const Sweep3Dev &sd, SwSmem &sm, int B0, int B1,
+                                      int lane, const int32_t *dummy, int s_first) {
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
       wbase[x] = dummy;
@@ -248,8 +254,10 @@ struct SwLoader {
 // One compute wave: row v0 = B0*kSwNW + w, lane j: column v1 = B1*64 + j.
 // kX0: the last row of a workgroup with one below it (stores X0); kX1: a row
 // of a workgroup with one to its right (lane 63 stores X1); kOrigin: wave 0
-// of workgroup (0, 0), whose lane 0 holds the origin.
-template <bool kX0, bool kX1, bool kOrigin>
+// of workgroup (0, 0), whose lane 0 holds the origin.  kEgf: end-gap-free
+// mode (Section 2's reading of free end gaps): every cell with some v_i = 0
+// scores 0 with no decision, and the best far-face cell is reported.
+template <bool kX0, bool kX1, bool kOrigin, bool kEgf>
 __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B0, int B1, int w,
                                           int j, bool lane_ok, int r0, int r1, int gap, int tag,
                                           int total) {
@@ -279,6 +287,22 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
   const int64_t x0inc = sd.n1 + 1;
   int32_t *const x1b = sd.x1 + (int64_t)B1 * sd.x1_plane + (int64_t)v0 * (sd.n2 + 1) - (63 + w);
   const bool lane63 = j == 63;
+  // end-gap-free: boundary lanes (v0 = 0 or v1 = 0), far lanes (v0 = n0 or
+  // v1 = n1; every lane's cell t = n2 is far too), and the row-major index of
+  // the lane's cell t = 0 (below 2^32, checked by the plan's set-up)
+  // the wave's cells t = 0 fall in steps w .. w + 63 and its cells t = n2 in
+  // steps n2 + w .. n2 + w + 63; outside those windows only waves holding
+  // a boundary or far lane test their cells (wave-uniform branches)
+  const bool ebz = v0 == 0 || v1 == 0;
+  const bool efar = v0 == sd.n0 || v1 == sd.n1;
+  const bool wbz = __builtin_amdgcn_ballot_w64(ebz) != 0;
+  const bool wfar = __builtin_amdgcn_ballot_w64(efar) != 0;
+  const uint32_t elin0 =
+      ((uint32_t)v0 * (uint32_t)(sd.n1 + 1) + (uint32_t)v1) * (uint32_t)(sd.n2 + 1);
+  // the lane's best far cell so far: its key (score << 3) and t; among equal
+  // scores the later t, whose row-major index is larger
+  int32_t eout = INT32_MIN;
+  int et = 0;
 
   int32_t outp = kNegKey;   // own output of the previous step (cell t - 1)
   int32_t b5 = kNegKey, b6 = kNegKey, b7 = kNegKey;
@@ -315,8 +339,20 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
       const int32_t c7 = b7 + p01 + (p02 + p12);
       int32_t best = max(max(max(c1, c2), c3), max(max(max(c4, c5), c6), c7));
       // the origin takes key 7: score 0, and the byte decodes to mask 0
-      if constexpr (kOrigin) best = (j == 0 && t == 0) ? 7 : best;
+      // (end-gap-free: every cell with some v_i = 0)
+      if constexpr (kEgf) {
+        if (wbz || (unsigned)(s - w) < 64u) best = (ebz || t == 0) ? 7 : best;
+      } else if constexpr (kOrigin) {
+        best = (j == 0 && t == 0) ? 7 : best;
+      }
       const int32_t out = valid ? (best & ~7) : kNegKey;
+      if constexpr (kEgf) {
+        if (wfar || (unsigned)(s - w - n2) < 64u) {
+          const bool take = valid && (efar ? out >= eout : t == n2);
+          eout = take ? out : eout;
+          et = take ? t : et;
+        }
+      }
       sm.ring[i & (kSwRing - 1)][w][j + 1] = out;
       // direction byte of cell t at (t - 1) mod 32 (see the flush below)
       stage[(t - 1) & 31] = (uint8_t)best;
@@ -352,6 +388,39 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
             *reinterpret_cast<const uint4 *>(stage + ((cl - 1) & 1) * 16);
     }
   }
+  if constexpr (kEgf) {
+    // the lane's far-face key (score << 32 | row-major index), the wave's
+    // best, then one atomic per wave
+    int64_t ekey = eout == INT32_MIN
+                       ? INT64_MIN
+                       : ((int64_t)(eout >> 3) << 32) | (int64_t)(elin0 + (uint32_t)et);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t o = __shfl_xor(ekey, d, 64);
+      ekey = o > ekey ? o : ekey;
+    }
+    if (j == 0 && ekey != INT64_MIN) atomicMax((long long *)sd.best, (long long)ekey);
+  }
+}
+
+// The row's variant: exchange stores (x0, x1) and the origin.
+template <bool kEgf>
+__device__ __forceinline__ void sweep_rows(const Sweep3Dev &sd, SwSmem &sm, int B0, int B1,
+                                           int w, int j, bool lane_ok, int r0, int r1, int gap,
+                                           int tag, int total, bool x0, bool x1) {
+  if (B0 == 0 && B1 == 0 && w == 0) {
+    if (x1)
+      sweep_row<false, true, true, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+    else
+      sweep_row<false, false, true, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+  } else if (x0 && x1)
+    sweep_row<true, true, false, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+  else if (x0)
+    sweep_row<true, false, false, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+  else if (x1)
+    sweep_row<false, true, false, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+  else
+    sweep_row<false, false, false, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
 }
 
 }  // namespace
@@ -472,22 +541,14 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
   const bool x0 = w == kSwNW - 1 && B0 < sd.nb0 - 1 && row_ok;
   const bool x1 = B1 < sd.nb1 - 1 && row_ok;
   sw_barrier();  // the loader's halo of steps -1 and 0 is in LDS
-  if (B0 == 0 && B1 == 0 && w == 0) {
-    if (x1)
-      sweep_row<false, true, true>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
-    else
-      sweep_row<false, false, true>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
-  } else if (x0 && x1)
-    sweep_row<true, true, false>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
-  else if (x0)
-    sweep_row<true, false, false>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
-  else if (x1)
-    sweep_row<false, true, false>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+  if (sd.egf)
+    sweep_rows<true>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total, x0, x1);
   else
-    sweep_row<false, false, false>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+    sweep_rows<false>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total, x0, x1);
 }
 
-int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, hipStream_t s) {
+int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, int32_t flags,
+                  hipStream_t s) {
   Sweep3Dev sd;
   sd.n0 = p.n[0];
   sd.n1 = p.n[1];
@@ -507,6 +568,8 @@ int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, hipStre
   sd.ts1 = p.tstride[1];
   sd.score_out = jd.score_out;
   sd.trace = jd.trace;
+  sd.egf = (flags & kEndGapsFree) != 0;
+  sd.best = &ctrl->best;
   // One workgroup per CU: a second one would share the SIMDs and stretch the
   // steps of both, and every step sits on the sweep's critical path.  The
   // launch asks for unused LDS beyond half of a CU's.

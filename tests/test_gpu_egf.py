@@ -113,3 +113,20 @@ def test_egf_full_size_k3_workload():
     dev.run()
     s1, r1 = dev.result()
     assert s1 == s0 and np.array_equal(r1, r0)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_egf_k3_both_fills(variant):
+    """k = 3 end-gap-free through the streaming fill (variant 1) and the tile
+    fill (variant 2), forced through the tuner table: full decision tensor
+    equal to the oracle's, shapes spanning several 8 x 64 workgroups and
+    16^3 tiles with ragged tails."""
+    rng = np.random.Generator(np.random.PCG64(7400 + variant))
+    sub, gap = protein_scoring()
+    try:
+        for lens in ((70, 130, 45), (9, 64, 17), (17, 1, 33), (33, 65, 0)):
+            msa.tune_set(msa.MSA_TUNE_PLAIN, 3, max(lens), variant, 0)
+            seqs = [rng.integers(0, 20, size=n).astype(np.uint8) for n in lens]
+            check_egf(seqs, sub, gap)
+    finally:
+        msa.tune_clear()

@@ -1,5 +1,6 @@
-"""Register budget of the persistent fill kernels (CPU only: a device-only
-compile of the kernel source with the compiler's resource-usage remarks).
+"""Register budget of the persistent fill kernels, and no scratch memory in
+any kernel (CPU only: device-only compiles of the kernel sources with the
+compiler's resource-usage remarks).
 
 The persistent fill kernels keep every workgroup that fits on a compute unit
 busy, so their throughput scales with occupancy.  A change that moves the job
@@ -36,15 +37,27 @@ def _demangle(names):
     return r.stdout.splitlines()
 
 
-@pytest.fixture(scope="module")
-def usage():
-    src = B.CSRC / "msa_kernels.hip"
+def _remarks(name):
+    src = B.CSRC / name
     cmd = [B.HIPCC, *B.COMMON, "--cuda-device-only", "-Rpass-analysis=kernel-resource-usage",
            "-c", str(src), "-o", "/dev/null"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    assert r.returncode == 0, r.stderr[-2000:]
+    return subprocess.run(cmd, capture_output=True, text=True)
+
+
+@pytest.fixture(scope="module")
+def usage():
+    from concurrent.futures import ThreadPoolExecutor
+    names = sorted(p.name for p in B.CSRC.glob("*.hip"))
+    with ThreadPoolExecutor(max_workers=len(names)) as ex:
+        runs = list(ex.map(_remarks, names))
+    for r in runs:
+        assert r.returncode == 0, r.stderr[-2000:]
+    return _parse("\n".join(r.stderr for r in runs))
+
+
+def _parse(stderr):
     names, vgprs, occ, scratch = [], [], [], []
-    for line in r.stderr.splitlines():
+    for line in stderr.splitlines():
         m = re.search(r"remark: Function Name: (\S+)", line)
         if m:
             names.append(m.group(1))
