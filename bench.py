@@ -234,7 +234,8 @@ def bench_served(n_jobs=20000, rates=SERVED_RATES, max_inflight=4, max_jobs=256,
                     "device_busy_fraction": round(busy / wall, 3),
                     "device_jobs_per_s": round(n_jobs / busy, 2) if busy > 0 else None,
                     "launches": st1["launches"] - st0["launches"],
-                    "device_max_pause_us": st1["max_pause_us"]})
+                    "device_max_pause_us": st1["max_pause_us"],
+                    "rerun_after_timeout": st1["rerun"] - st0["rerun"]})
         streams = [pre.run_stream(srv, rate) for rate in rates]
     out["streams"] = streams
     if streams:

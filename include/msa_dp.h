@@ -424,9 +424,20 @@ void msa_server_destroy(msa_server *srv);
  * ended with a status other than MSA_OK, [6] the last such status (MSA_OK if
  * none), [7] the longest pause in microseconds that a launch's fill saw
  * between two checks of a dependency wait, that is a time its queue did not
- * run (0 if none; such pauses do not count towards the wait's 2 s time-out).
+ * run (0 if none; such pauses do not count towards the wait's time-out,
+ * 250 ms in a batched launch),
+ * [8] jobs queued again because their launch's dependency wait timed out
+ * (each job is re-run at most once; a second time-out returns MSA_EDEVICE).
  * Returns MSA_OK or MSA_EINVAL. */
 int msa_server_stats(msa_server *srv, int64_t *out, int32_t n);
+
+/* msa_server_debug_wait_limit: the next `launches` launches of the server
+ * (in admission order) give up a dependency wait after `ticks` ticks of the
+ * 100 MHz clock instead of 250 ms, so that a test can exercise the time-out
+ * path from the host (every kernel still exits normally; the launch reports
+ * MSA_EDEVICE and the server re-runs its jobs once).  Returns MSA_OK or
+ * MSA_EINVAL (ticks < 1, launches < 0). */
+int msa_server_debug_wait_limit(msa_server *srv, int64_t ticks, int32_t launches);
 
 /* ------------------------------------------------------------------------
  * Host-side helpers (no device needed), exposed for tests and tools.

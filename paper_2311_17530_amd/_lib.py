@@ -115,6 +115,7 @@ _SIGS = {
                                        ctypes.c_int64]),
     "msa_server_destroy": (None, [c_vp]),
     "msa_server_stats": (ctypes.c_int, [c_vp, c_i64p, ctypes.c_int32]),
+    "msa_server_debug_wait_limit": (ctypes.c_int, [c_vp, ctypes.c_int64, ctypes.c_int32]),
     "msa_dp_score_bounds": (ctypes.c_int, [c_i32p, ctypes.c_int32, c_vp, ctypes.c_int32,
                                            ctypes.c_int32, c_i64p, c_i64p]),
     "msa_dp_check_scoring": (ctypes.c_int, [c_i32p, ctypes.c_int32, c_vp, ctypes.c_int32,
@@ -607,11 +608,17 @@ class Server:
 
     def stats(self):
         """``{"launches", "jobs", "busy_us", "span_us", "queued", "failed",
-        "last_failure", "max_pause_us"}`` so far."""
-        out = (ctypes.c_int64 * 8)()
-        _check(lib().msa_server_stats(self.h, out, 8), "msa_server_stats")
+        "last_failure", "max_pause_us", "rerun"}`` so far."""
+        out = (ctypes.c_int64 * 9)()
+        _check(lib().msa_server_stats(self.h, out, 9), "msa_server_stats")
         return dict(zip(("launches", "jobs", "busy_us", "span_us", "queued", "failed",
-                         "last_failure", "max_pause_us"), [int(x) for x in out]))
+                         "last_failure", "max_pause_us", "rerun"), [int(x) for x in out]))
+
+    def debug_wait_limit(self, ticks: int, launches: int):
+        """The next ``launches`` launches time out a dependency wait after
+        ``ticks`` ticks of the 100 MHz clock (``msa_server_debug_wait_limit``)."""
+        _check(lib().msa_server_debug_wait_limit(self.h, int(ticks), int(launches)),
+               "msa_server_debug_wait_limit")
 
     def close(self):
         if self.h:

@@ -92,9 +92,16 @@ struct Ctrl {
   int64_t max_pause;  // longest pause seen inside a dependency wait (ticks of
                       // the 100 MHz clock, see WaitClock); batched launches
                       // report and clear it
-  int32_t pad[40];
+  int64_t wd[3];      // the first dependency wait that timed out: the job's
+                      // first tile in the launch's numbering (JobDev::qbase),
+                      // the tile, and the mask of the predecessor dimensions
+                      // still missing (batched launches report it)
+  int64_t wait_limit;  // batched launches: dependency-wait time-out in 100 MHz
+                       // ticks (0: 2 s)
+  int32_t pad[32];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte slot");
+constexpr int64_t kBatchWaitTicks = 25000000;  // 250 ms: batched launches' time-out
 
 // Time a dependency wait has spent waiting, for its watchdog.  The 100 MHz
 // wall clock is read at every check of the wait, and only gaps shorter than
@@ -194,8 +201,9 @@ struct BatchArgs {
   int32_t *qjob, *qtile;      // the column queue: job index and first tile
   int32_t *flags;             // per-tile completion flags of all jobs
   int32_t *gstatus;           // output: the launch-wide status at its end
-                              // ([0]) and the longest pause of a dependency
-                              // wait (int64 at [2], 100 MHz ticks)
+                              // ([0]), the longest pause of a dependency wait
+                              // (int64 at [2], 100 MHz ticks) and the first
+                              // timed-out wait (Ctrl::wd, int64 at [4..9])
   int64_t tiles;              // tiles of all jobs
   int64_t cols;               // columns of all jobs (queue length)
   int32_t njobs;

@@ -263,13 +263,16 @@ struct HaloSlots {
 // exported.
 // scores: near-optimal mode: every cell's score is stored as well, in the
 // layout of the direction block (jd.scores + tile * DBS).
+// wlim: the dependency-wait time-out (100 MHz ticks), read by the kernel
+// once (a load in every wait would also wait for the tile's stores: one
+// counter tracks both).
 template <int K, int NT>
 __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int epoch,
                              Ctrl *ctrl, int32_t *jstatus, Smem<K> &sm,
                              const HaloSlots<K, NT> &hs, bool egf = false,
                              int64_t *best_key = nullptr, bool coopt = false,
                              bool prune = false, bool own0 = false, bool cols = false,
-                             bool scores = false) {
+                             bool scores = false, int64_t wlim = kWaitLimitTicks) {
   using C = Cfg<K>;
   constexpr int T = C::T;
   constexpr int E = C::E;
@@ -417,8 +420,16 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
         const int st = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (st == ST_EDEVICE) break;
-        if (wc.tick() > kWaitLimitTicks) {
-          atomicCAS(&ctrl->status, ST_OK, ST_EDEVICE);  // all lanes: idempotent
+        if (wc.tick() > wlim) {
+          // all lanes: idempotent; the wave whose lane made the change
+          // records the wait (every lane stores the same values)
+          const int prev = atomicCAS(&ctrl->status, ST_OK, ST_EDEVICE);
+          const uint64_t missing = __ballot(need);
+          if (__any(prev == ST_OK)) {
+            ctrl->wd[0] = jd.qbase;
+            ctrl->wd[1] = tile;
+            ctrl->wd[2] = (int64_t)missing;
+          }
           break;
         }
       }
@@ -1704,7 +1715,7 @@ constexpr size_t batch_smem_bytes() {
 // own0 and cols).
 template <int K, int NT>
 __device__ void batch_column(const JobDev &jd, int base, int epoch, Ctrl *ctrl, void *smraw,
-                             int &cur_k, const int8_t *&cur_sub) {
+                             int &cur_k, const int8_t *&cur_sub, int64_t wlim) {
   Smem<K> &sm = *reinterpret_cast<Smem<K> *>(smraw);
   if (cur_k != K || cur_sub != jd.sub) {
     __syncthreads();
@@ -1716,7 +1727,8 @@ __device__ void batch_column(const JobDev &jd, int base, int epoch, Ctrl *ctrl, 
   const HaloSlots<K, NT> hs(threadIdx.x);
   for (int c0 = 0; c0 < jd.P[0]; ++c0)
     process_tile<K, NT>(jd, jd.alpha, jd.gap, base + c0 * jd.tstride[0], epoch, ctrl,
-                        jd.jstatus, sm, hs, false, nullptr, false, false, c0 > 0, true);
+                        jd.jstatus, sm, hs, false, nullptr, false, false, c0 > 0, true, false,
+                        wlim);
 }
 
 // The job descriptors come as a kernel argument of their own (a fixed arena
@@ -1741,6 +1753,9 @@ void batch_fill_kernel(const BatchArgs *__restrict__ a,
   const int32_t total = __builtin_amdgcn_readfirstlane((int32_t)a->cols);
   __shared__ int32_t bcast;
   const int epoch = __hip_atomic_load(&ctrl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // the launch's dependency-wait time-out (0: the default), read once
+  const int64_t wl = __hip_atomic_load(&ctrl->wait_limit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int64_t wlim = wl > 0 ? wl : kWaitLimitTicks;
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) >> 6;
   int cur_k = -1;
   const int8_t *cur_sub = nullptr;
@@ -1757,13 +1772,13 @@ void batch_fill_kernel(const BatchArgs *__restrict__ a,
     const int tile = __builtin_amdgcn_readfirstlane(qtile[q]);
     const JobDev &jd = jobs[j];
     switch (jd.k) {
-      case 2: if constexpr (KLO <= 2 && 2 <= KHI) batch_column<2, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 3: if constexpr (KLO <= 3 && 3 <= KHI) batch_column<3, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 4: if constexpr (KLO <= 4 && 4 <= KHI) batch_column<4, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 5: if constexpr (KLO <= 5 && 5 <= KHI) batch_column<5, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 6: if constexpr (KLO <= 6 && 6 <= KHI) batch_column<6, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 7: if constexpr (KLO <= 7 && 7 <= KHI) batch_column<7, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
-      case 8: if constexpr (KLO <= 8 && 8 <= KHI) batch_column<8, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub); break;
+      case 2: if constexpr (KLO <= 2 && 2 <= KHI) batch_column<2, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub, wlim); break;
+      case 3: if constexpr (KLO <= 3 && 3 <= KHI) batch_column<3, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub, wlim); break;
+      case 4: if constexpr (KLO <= 4 && 4 <= KHI) batch_column<4, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub, wlim); break;
+      case 5: if constexpr (KLO <= 5 && 5 <= KHI) batch_column<5, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub, wlim); break;
+      case 6: if constexpr (KLO <= 6 && 6 <= KHI) batch_column<6, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub, wlim); break;
+      case 7: if constexpr (KLO <= 7 && 7 <= KHI) batch_column<7, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub, wlim); break;
+      case 8: if constexpr (KLO <= 8 && 8 <= KHI) batch_column<8, NT>(jd, tile, epoch, ctrl, smraw, cur_k, cur_sub, wlim); break;
       default: break;
     }
   }
@@ -1811,8 +1826,13 @@ __global__ void batch_zero_kernel(const BatchArgs *__restrict__ a) {
 __global__ void batch_finish_kernel(const BatchArgs *__restrict__ a, Ctrl *ctrl) {
   if (threadIdx.x == 0) {
     a->gstatus[0] = ctrl->status;
-    *reinterpret_cast<int64_t *>(a->gstatus + 2) = ctrl->max_pause;
+    int64_t *g64 = reinterpret_cast<int64_t *>(a->gstatus + 2);
+    g64[0] = ctrl->max_pause;
+    g64[1] = ctrl->wd[0];
+    g64[2] = ctrl->wd[1];
+    g64[3] = ctrl->wd[2];
     ctrl->max_pause = 0;
+    ctrl->wd[0] = ctrl->wd[1] = ctrl->wd[2] = 0;
     ctrl->head = 0;
     ctrl->status = ST_OK;
     ctrl->epoch = ctrl->epoch + 1;

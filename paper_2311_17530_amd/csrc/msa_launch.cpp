@@ -110,7 +110,23 @@ int Launch::init(int64_t bytes) {
     }
     cap_ = bytes;
   }
+  // Pinned staging and the four k classes' launch graphs are made here, once
+  // per arena, so that launches under load (a server's slots) allocate and
+  // instantiate nothing while other slots' persistent fills run.
+  int rc = ensure_host(1 << 20, 1 << 20);
+  if (rc) return rc;
+  for (int kc = 0; kc < 4; ++kc) (void)ensure_graph(kc, batch_grid(kc));
   return MSA_OK;
+}
+
+// Persistent workgroups of the batched fill: every one that fits, or the
+// tuned count per CU.
+int Launch::batch_grid(int kc) const {
+  int wpc = batch_occupancy(kc);
+  TuneChoice tc;
+  if (tune_get(kTuneBatch, kc, 0, &tc) && tc.wpc > 0) wpc = std::min(wpc, (int)tc.wpc);
+  const int grid = device_cu_count() * wpc;
+  return grid < 1 ? 1 : grid;
 }
 
 void Launch::drop_graphs() {
@@ -220,7 +236,7 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   const int64_t off_score = o;  o = a256(o + (int64_t)nj * 8);
   const int64_t off_len = o;    o = a256(o + (int64_t)nj * 8);
   const int64_t off_stat = o;   o = a256(o + (int64_t)nj * 4);
-  const int64_t off_gst = o;    o = a256(o + 16);
+  const int64_t off_gst = o;    o = a256(o + 40);
   std::vector<int64_t> job_out(nj);
   for (int i = 0; i < nj; ++i) {
     job_out[i] = o;
@@ -246,6 +262,10 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   Ctrl ctrl;
   memset(&ctrl, 0, sizeof(ctrl));
   ctrl.epoch = 1;
+  // A batched dependency wait is bounded by one job's tile chain (a few ms
+  // even for large jobs), so a launch gives up after 250 ms instead of the
+  // plain fill's 2 s: a launch that times out is re-run sooner.
+  ctrl.wait_limit = wait_limit_ > 0 ? wait_limit_ : kBatchWaitTicks;
   memcpy(h + off_ctrl, &ctrl, sizeof(ctrl));
   for (auto &kv : subs)
     memcpy(h + kv.second, kv.first.data(), kv.first.size() - 1);
@@ -315,6 +335,7 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
     meta_[i].k = j.k;
     meta_[i].cap = sz[i].cap;
     meta_[i].aln_off = job_out[i] - off_out;
+    meta_[i].qbase = jt[i];
   }
 
   // The queue holds tile columns along dimension 0 (a workgroup computes a
@@ -357,12 +378,7 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   memcpy(h + off_args, &args, sizeof(args));
 
   // ---- enqueue: inputs, the launch sequence (a graph replay), outputs ----
-  // persistent workgroups: every one that fits, or the tuned count per CU
-  int wpc = batch_occupancy(kc);
-  TuneChoice tc;
-  if (tune_get(kTuneBatch, kc, 0, &tc) && tc.wpc > 0) wpc = std::min(wpc, (int)tc.wpc);
-  int grid = device_cu_count() * wpc;
-  if (grid < 1) grid = 1;
+  const int grid = batch_grid(kc);
   const bool graph = ensure_graph(kc, grid) == 0;
   bool ok = hipEventRecord(start_, stream_) == hipSuccess;
   ok = ok && hipMemcpyAsync(d_, h, (size_t)in_bytes, hipMemcpyHostToDevice, stream_) == hipSuccess;
@@ -409,6 +425,19 @@ int64_t Launch::device_max_pause_us() const {
   const int nj = (int)meta_.size();
   const int64_t off_gst = 2 * a256((int64_t)nj * 8) + a256((int64_t)nj * 4);
   return *reinterpret_cast<const int64_t *>(h_out_ + off_gst + 8) / 100;  // 100 MHz ticks
+}
+
+bool Launch::device_timeout(int *job, int64_t *tile, int64_t *missing) const {
+  const int nj = (int)meta_.size();
+  const int64_t off_gst = 2 * a256((int64_t)nj * 8) + a256((int64_t)nj * 4);
+  const int64_t *w = reinterpret_cast<const int64_t *>(h_out_ + off_gst + 16);
+  if (device_status() == MSA_OK) return false;
+  *job = -1;
+  for (int i = 0; i < nj; ++i)
+    if (meta_[i].qbase == w[0]) *job = i;
+  *tile = w[1];
+  *missing = w[2];
+  return true;
 }
 
 void Launch::result(int i, LaunchResult *out) const {

@@ -66,18 +66,28 @@ class Launch {
   // not run (its queue preempted); such pauses do not count towards the
   // wait's time-out.  0 when there was none.
   int64_t device_max_pause_us() const;
+  // After ready()/wait() of a launch whose device status is not MSA_OK: the
+  // first dependency wait that timed out, as the index of its job among the
+  // staged ones (-1 if not found), its tile and the mask of the predecessor
+  // dimensions it still missed.  False when the launch did not time out.
+  bool device_timeout(int *job, int64_t *tile, int64_t *missing) const;
   int njobs() const { return (int)meta_.size(); }
   // After ready()/wait(): the launch's device interval (from its first copy
   // to its last) in milliseconds after `ref`, an event recorded earlier on
   // the same device.  False if the events cannot be read.
   bool interval_ms(hipEvent_t ref, float *t0, float *t1) const;
   void release() { busy_ = false; meta_.clear(); }
+  // Dependency-wait time-out of the next launches, in 100 MHz ticks (0: the
+  // batched default, kBatchWaitTicks); a host-side way to exercise time-out
+  // handling.
+  void set_wait_limit(int64_t ticks) { wait_limit_ = ticks; }
 
  private:
   struct Meta {
     int k = 0;
     int64_t cap = 0;
     int64_t aln_off = 0;  // offset of the rows in the host output image
+    int64_t qbase = 0;    // first tile of the job in the launch's numbering
   };
   int device_ = -1;
   hipStream_t stream_ = nullptr;
@@ -94,6 +104,7 @@ class Launch {
   std::vector<Meta> meta_;
   bool busy_ = false;
   int launch_status_ = MSA_OK;
+  int64_t wait_limit_ = 0;
   // The launch sequence of each k class, captured once on this arena (its
   // arguments are the arena's fixed batch descriptor and control block) and
   // replayed for every batch; dropped when the arena is reallocated.
@@ -101,6 +112,7 @@ class Launch {
   int graph_grid_[4] = {};  // the fill grid each graph was captured with
   bool graph_failed_[4] = {};
   int ensure_host(int64_t in_bytes, int64_t out_bytes);
+  int batch_grid(int kc) const;
   int ensure_graph(int kc, int grid);
   void drop_graphs();
 };

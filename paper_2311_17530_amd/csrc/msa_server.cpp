@@ -37,6 +37,7 @@ struct Pending {
   std::vector<int8_t> sub;
   int64_t bytes = 0;
   int64_t ntiles = 0;
+  int retries = 0;  // launches re-run after a dependency-wait time-out
 };
 
 struct Done {
@@ -83,6 +84,11 @@ struct msa_server {
   // longest pause a launch's fill saw inside a dependency wait (its queue
   // not running), microseconds
   int64_t max_pause_us = 0;
+  int n_timeouts = 0;  // time-outs reported on stderr so far
+  int64_t n_rerun = 0;  // jobs queued again after their launch timed out
+  // msa_server_debug_wait_limit: launches left with a short wait limit
+  int64_t dbg_wait_ticks = 0;
+  int dbg_launches = 0;
   std::vector<std::pair<float, float>> intervals;
 
   void run();
@@ -139,6 +145,9 @@ bool msa_server::admit(Slot &s, int free_slots) {
     it = queue.erase(it);
   }
   if (grp.empty()) return false;
+  // debug: the next dbg_launches launches take a short dependency-wait limit
+  s.launch->set_wait_limit(dbg_launches > 0 ? dbg_wait_ticks : 0);
+  if (dbg_launches > 0) --dbg_launches;
   const int rc = s.launch->start(grp);
   for (uint64_t t : s.tickets) running[t] = 0;
   if (rc != MSA_OK) {
@@ -161,11 +170,38 @@ void msa_server::collect(Slot &s) {
   float t0 = 0.f, t1 = 0.f;
   if (ref && s.launch->interval_ms(ref, &t0, &t1)) intervals.emplace_back(t0, t1);
   ++n_launches;
-  n_jobs += (int64_t)s.tickets.size();
   max_pause_us = std::max(max_pause_us, s.launch->device_max_pause_us());
+  int jb = -1;
+  int64_t tile = 0, missing = 0;
+  const bool timed_out = s.launch->device_timeout(&jb, &tile, &missing);
+  {
+    if (timed_out && n_timeouts < 4) {
+      ++n_timeouts;
+      fprintf(stderr, "msa server: a launch of %zu jobs timed out in a dependency wait: job %d",
+              s.tickets.size(), jb);
+      if (jb >= 0 && jb < (int)s.jobs.size()) {
+        const msa_job &j = s.jobs[jb]->job;
+        fprintf(stderr, " (k = %d, lengths", j.k);
+        for (int d = 0; d < j.k; ++d) fprintf(stderr, " %lld", (long long)j.lens[d]);
+        fprintf(stderr, ")");
+      }
+      fprintf(stderr, ", tile %lld, missing predecessor dimensions 0x%llx\n", (long long)tile,
+              (unsigned long long)missing);
+    }
+  }
+  // A launch whose dependency wait timed out is re-run once: its jobs go back
+  // to the front of the queue (the result of a re-run is the same exact
+  // alignment); a job whose second launch times out too returns the status.
+  std::vector<std::unique_ptr<Pending>> again;
   for (size_t i = 0; i < s.tickets.size(); ++i) {
     LaunchResult r;
     s.launch->result((int)i, &r);
+    if (timed_out && r.status == MSA_EDEVICE && s.jobs[i]->retries == 0) {
+      ++s.jobs[i]->retries;
+      running.erase(s.tickets[i]);
+      again.push_back(std::move(s.jobs[i]));
+      continue;
+    }
     Done &d = done[s.tickets[i]];
     d.status = r.status;
     if (r.status != MSA_OK)
@@ -179,6 +215,9 @@ void msa_server::collect(Slot &s) {
     d.aln.swap(r.aln);
     running.erase(s.tickets[i]);
   }
+  n_jobs += (int64_t)(s.tickets.size() - again.size());
+  n_rerun += (int64_t)again.size();
+  for (auto it = again.rbegin(); it != again.rend(); ++it) queue.push_front(std::move(*it));
   s.tickets.clear();
   s.jobs.clear();
   s.launch->release();
@@ -353,11 +392,19 @@ extern "C" int msa_server_stats(msa_server *srv, int64_t *out, int32_t n) {
     last = std::max(last, (double)x.second);
   }
   if (open) busy += hi - lo;
-  const int64_t v[8] = {srv->n_launches, srv->n_jobs, (int64_t)(busy * 1000.0),
+  const int64_t v[9] = {srv->n_launches, srv->n_jobs, (int64_t)(busy * 1000.0),
                         open ? (int64_t)((last - first) * 1000.0) : 0,
                         (int64_t)srv->queue.size(), srv->n_failed, srv->last_failure,
-                        srv->max_pause_us};
-  for (int i = 0; i < n && i < 8; ++i) out[i] = v[i];
+                        srv->max_pause_us, srv->n_rerun};
+  for (int i = 0; i < n && i < 9; ++i) out[i] = v[i];
+  return MSA_OK;
+}
+
+extern "C" int msa_server_debug_wait_limit(msa_server *srv, int64_t ticks, int32_t launches) {
+  if (!srv || ticks < 1 || launches < 0) return MSA_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->dbg_wait_ticks = ticks;
+  srv->dbg_launches = launches;
   return MSA_OK;
 }
 

@@ -220,6 +220,37 @@ def test_server_stream_of_served_jobs():
         assert out[i][1] == s0 and np.array_equal(out[i][2], r0)
 
 
+def test_server_reruns_a_launch_that_timed_out():
+    """Time-out handling, forced from the host: the first launches of the
+    server give up a dependency wait after one tick of the 100 MHz clock
+    (every kernel still exits normally).  Their jobs are re-run once and
+    return the plain path's alignment; with the short limit on every launch,
+    a job whose second launch times out returns MSA_EDEVICE."""
+    jobs = served_jobs(400, seed=9)
+    plain = [msa.align(j.seqs, j.sub, j.gap) for j in jobs]
+    with msa.Server(max_inflight=2, max_jobs_per_launch=64) as srv:
+        srv.debug_wait_limit(1, 2)
+        tickets = [srv.submit(j.seqs, j.sub, j.gap) for j in jobs[:200]]
+        out = [srv.wait(t, 60_000_000) for t in tickets]
+        stats = srv.stats()
+    say("forced time-outs, first launches only: %s" % stats)
+    assert stats["rerun"] > 0 and stats["failed"] == 0, stats
+    for (st, score, rows), (s1, r1) in zip(out, plain):
+        assert st == msa.MSA_OK and score == s1 and np.array_equal(rows, r1)
+    with msa.Server(max_inflight=2, max_jobs_per_launch=64) as srv:
+        srv.debug_wait_limit(1, 1 << 20)
+        tickets = [srv.submit(j.seqs, j.sub, j.gap) for j in jobs]
+        out = [srv.wait(t, 60_000_000) for t in tickets]
+        stats = srv.stats()
+    say("forced time-outs, every launch: %s" % stats)
+    st = [o[0] for o in out]
+    assert set(st) <= {msa.MSA_OK, msa.MSA_EDEVICE}, set(st)
+    assert st.count(msa.MSA_EDEVICE) == stats["failed"] > 0 and stats["rerun"] > 0, stats
+    for (s, score, rows), (s1, r1) in zip(out, plain):
+        if s == msa.MSA_OK:
+            assert score == s1 and np.array_equal(rows, r1)
+
+
 def test_server_errors_and_shutdown():
     sub, gap = dna_scoring()
     with msa.Server(hbm_budget_bytes=64 << 20, max_inflight=2) as srv:
