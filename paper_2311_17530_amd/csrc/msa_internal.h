@@ -92,13 +92,15 @@ struct Ctrl {
   int64_t max_pause;  // longest pause seen inside a dependency wait (ticks of
                       // the 100 MHz clock, see WaitClock); batched launches
                       // report and clear it
-  int64_t wd[3];      // the first dependency wait that timed out: the job's
+  int64_t wd[6];      // the first dependency wait that timed out: the job's
                       // first tile in the launch's numbering (JobDev::qbase),
-                      // the tile, and the mask of the predecessor dimensions
-                      // still missing (batched launches report it)
+                      // the tile, the mask of the predecessor dimensions
+                      // still missing, the first missing predecessor tile,
+                      // the value its flag held, and the queue head then
+                      // (batched launches report it)
   int64_t wait_limit;  // batched launches: dependency-wait time-out in 100 MHz
                        // ticks (0: 2 s)
-  int32_t pad[32];
+  int32_t pad[26];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte slot");
 constexpr int64_t kBatchWaitTicks = 25000000;  // 250 ms: batched launches' time-out

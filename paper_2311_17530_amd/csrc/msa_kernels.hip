@@ -426,9 +426,18 @@ __device__ void process_tile(const JobDev &jd, int alpha, int gap, int tile, int
           const int prev = atomicCAS(&ctrl->status, ST_OK, ST_EDEVICE);
           const uint64_t missing = __ballot(need);
           if (__any(prev == ST_OK)) {
+            // the first missing predecessor: its tile and the flag it holds
+            const int lm = missing ? (int)__builtin_ctzll(missing) : 0;
+            const int64_t ptile =
+                __shfl((int)(f - jd.flags), lm, 64);
+            const int32_t pval = __shfl(
+                __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), lm, 64);
             ctrl->wd[0] = jd.qbase;
             ctrl->wd[1] = tile;
             ctrl->wd[2] = (int64_t)missing;
+            ctrl->wd[3] = ptile;
+            ctrl->wd[4] = pval;
+            ctrl->wd[5] = __hip_atomic_load(&ctrl->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
           break;
         }
@@ -1828,11 +1837,12 @@ __global__ void batch_finish_kernel(const BatchArgs *__restrict__ a, Ctrl *ctrl)
     a->gstatus[0] = ctrl->status;
     int64_t *g64 = reinterpret_cast<int64_t *>(a->gstatus + 2);
     g64[0] = ctrl->max_pause;
-    g64[1] = ctrl->wd[0];
-    g64[2] = ctrl->wd[1];
-    g64[3] = ctrl->wd[2];
+    for (int q = 0; q < 6; ++q) {
+      g64[1 + q] = ctrl->wd[q];
+      ctrl->wd[q] = 0;
+    }
+    g64[7] = a->cols;
     ctrl->max_pause = 0;
-    ctrl->wd[0] = ctrl->wd[1] = ctrl->wd[2] = 0;
     ctrl->head = 0;
     ctrl->status = ST_OK;
     ctrl->epoch = ctrl->epoch + 1;

@@ -116,6 +116,15 @@ int Launch::init(int64_t bytes) {
   int rc = ensure_host(1 << 20, 1 << 20);
   if (rc) return rc;
   for (int kc = 0; kc < 4; ++kc) (void)ensure_graph(kc, batch_grid(kc));
+  // The stream's first kernel and its first copies each way make the runtime
+  // create the hardware queues behind them; doing it here keeps that out of
+  // the time when other slots' persistent fills run (the queue list changes
+  // then, and running queues are preempted).
+  if (hipMemsetAsync(d_, 0, 256, stream_) != hipSuccess ||
+      hipMemcpyAsync(d_, h_in_, 256, hipMemcpyHostToDevice, stream_) != hipSuccess ||
+      hipMemcpyAsync(h_out_, d_, 256, hipMemcpyDeviceToHost, stream_) != hipSuccess ||
+      hipStreamSynchronize(stream_) != hipSuccess)
+    return MSA_EDEVICE;
   return MSA_OK;
 }
 
@@ -236,7 +245,7 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   const int64_t off_score = o;  o = a256(o + (int64_t)nj * 8);
   const int64_t off_len = o;    o = a256(o + (int64_t)nj * 8);
   const int64_t off_stat = o;   o = a256(o + (int64_t)nj * 4);
-  const int64_t off_gst = o;    o = a256(o + 40);
+  const int64_t off_gst = o;    o = a256(o + 72);
   std::vector<int64_t> job_out(nj);
   for (int i = 0; i < nj; ++i) {
     job_out[i] = o;
@@ -427,7 +436,7 @@ int64_t Launch::device_max_pause_us() const {
   return *reinterpret_cast<const int64_t *>(h_out_ + off_gst + 8) / 100;  // 100 MHz ticks
 }
 
-bool Launch::device_timeout(int *job, int64_t *tile, int64_t *missing) const {
+bool Launch::device_timeout(int *job, int64_t *tile, int64_t *missing, int64_t more[4]) const {
   const int nj = (int)meta_.size();
   const int64_t off_gst = 2 * a256((int64_t)nj * 8) + a256((int64_t)nj * 4);
   const int64_t *w = reinterpret_cast<const int64_t *>(h_out_ + off_gst + 16);
@@ -437,6 +446,8 @@ bool Launch::device_timeout(int *job, int64_t *tile, int64_t *missing) const {
     if (meta_[i].qbase == w[0]) *job = i;
   *tile = w[1];
   *missing = w[2];
+  if (more)
+    for (int q = 0; q < 4; ++q) more[q] = w[3 + q];
   return true;
 }
 

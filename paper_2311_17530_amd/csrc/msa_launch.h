@@ -69,8 +69,11 @@ class Launch {
   // After ready()/wait() of a launch whose device status is not MSA_OK: the
   // first dependency wait that timed out, as the index of its job among the
   // staged ones (-1 if not found), its tile and the mask of the predecessor
-  // dimensions it still missed.  False when the launch did not time out.
-  bool device_timeout(int *job, int64_t *tile, int64_t *missing) const;
+  // dimensions it still missed; `more` (if not null) receives the first
+  // missing predecessor tile, the value its flag held, the queue head then and
+  // the queue length.  False when the launch did not time out.
+  bool device_timeout(int *job, int64_t *tile, int64_t *missing,
+                      int64_t more[4] = nullptr) const;
   int njobs() const { return (int)meta_.size(); }
   // After ready()/wait(): the launch's device interval (from its first copy
   // to its last) in milliseconds after `ref`, an event recorded earlier on

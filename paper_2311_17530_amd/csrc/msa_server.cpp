@@ -172,8 +172,8 @@ void msa_server::collect(Slot &s) {
   ++n_launches;
   max_pause_us = std::max(max_pause_us, s.launch->device_max_pause_us());
   int jb = -1;
-  int64_t tile = 0, missing = 0;
-  const bool timed_out = s.launch->device_timeout(&jb, &tile, &missing);
+  int64_t tile = 0, missing = 0, more[4] = {};
+  const bool timed_out = s.launch->device_timeout(&jb, &tile, &missing, more);
   {
     if (timed_out && n_timeouts < 4) {
       ++n_timeouts;
@@ -185,8 +185,11 @@ void msa_server::collect(Slot &s) {
         for (int d = 0; d < j.k; ++d) fprintf(stderr, " %lld", (long long)j.lens[d]);
         fprintf(stderr, ")");
       }
-      fprintf(stderr, ", tile %lld, missing predecessor dimensions 0x%llx\n", (long long)tile,
-              (unsigned long long)missing);
+      fprintf(stderr,
+              ", tile %lld, missing predecessor dimensions 0x%llx (tile %lld, flag %lld), "
+              "queue head %lld of %lld\n",
+              (long long)tile, (unsigned long long)missing, (long long)more[0],
+              (long long)more[1], (long long)more[2], (long long)more[3]);
     }
   }
   // A launch whose dependency wait timed out is re-run once: its jobs go back
