@@ -390,10 +390,13 @@ int msa_dp_autotune_batch(const msa_job *jobs, int32_t njobs, int32_t reps, int3
 /* ------------------------------------------------------------------------
  * Served path: a request loop that admits jobs as device memory (the HBM
  * budget) and launch slots free up, keeps their state on the device and runs
- * several persistent launches concurrently (continuous batching).
+ * several persistent launches at once (continuous batching).  Small launches
+ * overlap on the device; a launch of 32 jobs or more runs alone (it waits for
+ * the launches in flight and later ones wait for it, on the device).
  *
  * msa_server_create: hbm_budget_bytes (0 = default), max_inflight = maximum
- *   concurrent launches (streams), max_jobs_per_launch.  NULL on failure.
+ *   launches in flight (launch slots, each with its share of the budget),
+ *   max_jobs_per_launch.  NULL on failure.
  * msa_server_submit: copies the job's inputs; *ticket identifies it.
  *   MSA_EINVAL / MSA_ERANGE for invalid jobs, MSA_ENOMEM when the job alone
  *   exceeds the whole budget, MSA_ESHUTDOWN after destroy started.

@@ -88,11 +88,15 @@ Launch::~Launch() {
   if (h_out_) (void)hipHostFree(h_out_);
   if (done_) (void)hipEventDestroy(done_);
   if (start_) (void)hipEventDestroy(start_);
-  if (stream_) (void)hipStreamDestroy(stream_);
+  if (stream_ && own_stream_) (void)hipStreamDestroy(stream_);
 }
 
-int Launch::init(int64_t bytes) {
+int Launch::init(int64_t bytes, hipStream_t shared) {
   if (hipGetDevice(&device_) != hipSuccess) return MSA_EDEVICE;
+  if (!stream_ && shared) {
+    stream_ = shared;
+    own_stream_ = false;
+  }
   if (!stream_ && hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking) != hipSuccess)
     return MSA_EDEVICE;
   if (!done_ && hipEventCreateWithFlags(&done_, hipEventDefault) != hipSuccess)
@@ -196,7 +200,8 @@ int Launch::ensure_host(int64_t in_bytes, int64_t out_bytes) {
   return MSA_OK;
 }
 
-int Launch::start(const std::vector<const msa_job *> &jobs) {
+int Launch::start(const std::vector<const msa_job *> &jobs,
+                  const std::vector<hipEvent_t> &after) {
   if (busy_ || jobs.empty()) return MSA_EINVAL;
   const int nj = (int)jobs.size();
   const int kc = kclass_of(jobs[0]->k);
@@ -389,7 +394,9 @@ int Launch::start(const std::vector<const msa_job *> &jobs) {
   // ---- enqueue: inputs, the launch sequence (a graph replay), outputs ----
   const int grid = batch_grid(kc);
   const bool graph = ensure_graph(kc, grid) == 0;
-  bool ok = hipEventRecord(start_, stream_) == hipSuccess;
+  bool ok = true;
+  for (hipEvent_t e : after) ok = ok && hipStreamWaitEvent(stream_, e, 0) == hipSuccess;
+  ok = ok && hipEventRecord(start_, stream_) == hipSuccess;
   ok = ok && hipMemcpyAsync(d_, h, (size_t)in_bytes, hipMemcpyHostToDevice, stream_) == hipSuccess;
   if (graph)
     ok = ok && hipGraphLaunch(graph_[kc], stream_) == hipSuccess;

@@ -41,16 +41,22 @@ class Launch {
   Launch(const Launch &) = delete;
   Launch &operator=(const Launch &) = delete;
 
-  // Arena and stream set-up on the current device; arena of `bytes`.
-  int init(int64_t bytes);
+  // Arena and stream set-up on the current device; arena of `bytes`.  With
+  // `shared`, the launch runs on that stream (owned by the caller) instead of
+  // one of its own.
+  int init(int64_t bytes, hipStream_t shared = nullptr);
   int64_t capacity() const { return cap_; }
 
   // Fixed bytes of a launch besides the jobs (control block, tables, queue).
   static int64_t overhead_bytes(int njobs, int64_t ntiles_total);
 
-  // Stages the given valid jobs (all of one k class) and enqueues the launch.
+  // Stages the given valid jobs (all of one k class) and enqueues the launch,
+  // on the device after the events in `after` (other launches' done events).
   // Returns MSA_OK, MSA_ENOMEM if they do not fit, or MSA_EDEVICE.
-  int start(const std::vector<const msa_job *> &jobs);
+  int start(const std::vector<const msa_job *> &jobs,
+            const std::vector<hipEvent_t> &after = {});
+  // Recorded after the launch's output copy (a later launch may wait on it).
+  hipEvent_t done_event() const { return done_; }
   bool busy() const { return busy_; }
   bool ready();            // launch finished (non-blocking)
   int wait();              // block until finished
@@ -94,6 +100,7 @@ class Launch {
   };
   int device_ = -1;
   hipStream_t stream_ = nullptr;
+  bool own_stream_ = true;
   hipEvent_t start_ = nullptr;  // before the input copy (timing)
   hipEvent_t done_ = nullptr;   // after the output copy (timing)
   char *d_ = nullptr;

@@ -1,11 +1,17 @@
 // msa_server.cpp -- served path: a request loop with continuous batching.
 //
 // Jobs are submitted at any time.  A worker thread keeps up to `max_inflight`
-// batched persistent launches running on separate streams; whenever a launch
-// slot is free it admits the oldest queued jobs (of one k class) that fit the
-// slot's share of the HBM budget, so requests that arrive while others run
-// start as soon as a slot and its memory free up, and launches overlap on the
-// device.  Finished results wait in a table until polled.
+// batched persistent launches in flight, each slot on a stream of its own;
+// whenever a slot is free it admits the oldest queued jobs (of one k class)
+// that fit the slot's share of the HBM budget, so requests that arrive while
+// others run start as soon as a slot and its memory free up.  Small launches
+// (the latency regime) overlap on the device.  A large launch (kLargeLaunch
+// jobs or more, the saturated regime) runs alone: its stream waits for every
+// launch in flight, and every later launch waits for it, through events, so
+// the host still stages ahead.  Large persistent fills running side by side
+// on several hardware queues had those queues preempted, and now and then a
+// dependency wait of one of them timed out; one at a time they were also
+// faster.  Finished results wait in a table until polled.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,8 +55,12 @@ struct Done {
   std::vector<uint8_t> aln;
 };
 
+// Launches of at least this many jobs run alone on the device.
+constexpr int kLargeLaunch = 32;
+
 struct Slot {
   std::unique_ptr<Launch> launch;
+  bool large = false;  // the launch in flight is a large one
   std::vector<uint64_t> tickets;
   std::vector<std::unique_ptr<Pending>> jobs;  // inputs stay alive while staged
 };
@@ -148,7 +158,13 @@ bool msa_server::admit(Slot &s, int free_slots) {
   // debug: the next dbg_launches launches take a short dependency-wait limit
   s.launch->set_wait_limit(dbg_launches > 0 ? dbg_wait_ticks : 0);
   if (dbg_launches > 0) --dbg_launches;
-  const int rc = s.launch->start(grp);
+  // device order: a large launch after every launch in flight, any launch
+  // after a large one in flight
+  s.large = (int)grp.size() >= kLargeLaunch;
+  std::vector<hipEvent_t> after;
+  for (auto &o : slots)
+    if (&o != &s && o.launch->busy() && (s.large || o.large)) after.push_back(o.launch->done_event());
+  const int rc = s.launch->start(grp, after);
   for (uint64_t t : s.tickets) running[t] = 0;
   if (rc != MSA_OK) {
     note_failure(rc, (int64_t)s.tickets.size(), "launch set-up");
