@@ -328,3 +328,10 @@ def test_tuner_table_without_device():
         assert e.value.status == msa.MSA_EINVAL
     msa.tune_clear()
     assert msa.tune_get(msa.MSA_TUNE_PLAIN, 3, 512) == (0, 0)
+
+
+def test_server_debug_wait_limit_rejects_bad_arguments():
+    lib = msa.lib()
+    # a null server and bad values are refused before anything touches a device
+    assert lib.msa_server_debug_wait_limit(None, 1, 1) == msa.MSA_EINVAL
+    assert lib.msa_server_stats(None, None, 0) == msa.MSA_EINVAL
