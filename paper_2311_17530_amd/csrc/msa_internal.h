@@ -184,11 +184,13 @@ constexpr int kNoMaxTotal = 4096;
 constexpr int kCoMaxK = 3;
 constexpr int kCoMaxTotal = 32768;
 
-// Streaming fill of k = 3 (msa_sweep3.hip): a workgroup owns kSwNW rows
+// Streaming fill of k = 3 (msa_sweep3.hip): a workgroup owns kSwRows rows
 // (dimension 0) x 64 lanes (dimension 1) of lines along dimension 2 and
 // sweeps the whole length; neighbouring workgroups exchange their boundary
 // lines through tagged values in two exchange regions of the workspace.
-constexpr int kSwNW = 8;           // compute waves (rows) per workgroup
+constexpr int kSwNW = 8;           // compute waves per workgroup
+constexpr int kSwRPW = 2;          // rows per compute wave
+constexpr int kSwRows = kSwNW * kSwRPW;  // rows per workgroup
 constexpr int kSwLanes = 64;       // lanes (dimension-1 cells) per wave
 constexpr int kSwSeqMax = 16384;   // longest third sequence (kept in LDS)
 constexpr int kSwSubMax = 32;      // largest alphabet (matrix kept in LDS)

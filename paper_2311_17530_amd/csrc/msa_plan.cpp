@@ -116,7 +116,7 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
     q.off_bcnt = o;   o = align256(o + (int64_t)q.nblocks * 4);
   }
   if (k == 3) {
-    q.sw_nb0 = (q.n[0] + 1 + kSwNW - 1) / kSwNW;
+    q.sw_nb0 = (q.n[0] + 1 + kSwRows - 1) / kSwRows;
     q.sw_nb1 = (q.n[1] + 1 + kSwLanes - 1) / kSwLanes;
     q.x0_plane = ((int64_t)q.n[1] + q.n[2] + 1) * ((int64_t)q.n[1] + 1);
     q.x1_plane = ((int64_t)q.n[0] + 1) * ((int64_t)q.n[2] + 1);

@@ -6,27 +6,32 @@
 // instead of tile by tile:
 //
 //   - Lines.  A line is the run of cells (v0, v1, 0..n2) along dimension 2.
-//     A workgroup owns kSwNW x 64 lines: rows v0 = B0*kSwNW + w (wave w) and
-//     columns v1 = B1*64 + j (lane j), and sweeps them over the whole length
-//     in steps: at block step s, lane j of wave w computes cell t = s - j - w
-//     of its line.  Every neighbour v - b of that cell was computed by the
-//     same lane, the lane to its left (v1 - 1) or the wave above (v0 - 1) one
-//     to three steps earlier, so a step needs no wait beyond one barrier.
+//     A workgroup owns kSwRows x 64 lines: rows v0 = B0*kSwRows + 2w and
+//     2w + 1 (wave w's upper and lower row) and columns v1 = B1*64 + j (lane
+//     j), and sweeps them over the whole length in steps: at block step s,
+//     lane j of wave w computes cell t = s - j - w of both its lines, the
+//     upper one first.  Every neighbour v - b of that cell was computed by
+//     the same lane (in this step for the lower row's neighbours in the
+//     upper row), the lane to its left (v1 - 1) or the wave above (v0 - 1)
+//     one to three steps earlier, so a step needs no wait beyond one barrier.
+//     Two rows per wave halve the workgroups along dimension 0, and with
+//     them the hand-offs between workgroups on the sweep's critical path.
 //   - Exchange inside a wave: lane j - 1's previous output arrives by a DPP
 //     wave shift (wave_shr:1); outputs of two steps back are kept in
-//     registers.  Between waves: each wave writes its outputs to an LDS ring
-//     of 4 steps, read by the wave below one or two steps later.  Entry 0 of
-//     a ring row is the value of the row's lane -1 (the workgroup to the
-//     left), so every lane reads its neighbours at fixed offsets.
-//   - Exchange between workgroups: the outputs of the last wave go to region
-//     X0 and those of lane 63 of every wave to region X1, each value tagged
-//     with the launch's epoch in its low 3 bits (keys keep those bits clear).
-//     A loader wave (wave kSwNW) does every global access of the exchange:
-//     it stores this workgroup's boundary outputs one step after they are
-//     computed, and loads the neighbours' values kSwPf steps ahead, checks
-//     their tags (reloading while any is stale) and writes them to LDS one
-//     step before they are read.  Compute waves issue no global load, and
-//     their only stores (direction bytes, every 16 steps) are never waited on.
+//     registers.  Between waves: each wave writes its lower row's outputs to
+//     an LDS ring of 4 steps, read by the wave below one or two steps later.
+//     Entry 0 of a ring row is the value of the row's lane -1 (the workgroup
+//     to the left), so every lane reads its neighbours at fixed offsets; the
+//     upper rows' lane -1 values have an array of their own (h0).
+//   - Exchange between workgroups: the outputs of the last row go to region
+//     X0 and those of lane 63 of every row to region X1, each value tagged
+//     with the launch's epoch in its low 3 bits (keys keep those bits clear);
+//     the compute waves store them as they compute them.  A loader wave
+//     (wave kSwNW) does every global load of the exchange: it loads the
+//     neighbours' values kSwPf steps ahead, checks their tags (reloading
+//     while any is stale) and writes them to LDS one step before they are
+//     read.  Compute waves issue no global load, and no wave waits on their
+//     stores (exchange values, and direction bytes every 16 steps).
 //   - Workgroups take tickets in order of their block diagonal B0 + B1; a
 //     workgroup only waits for workgroups with smaller tickets, which are
 //     already running, so the grid cannot deadlock.
@@ -62,6 +67,7 @@ constexpr int kSwDbs = kSwT * kSwT * kSwT;
 constexpr int64_t kSwWaitTicks = 200000000;  // 2 s of waiting (WaitClock ticks)
 
 static_assert(kSwDbs == 4096, "direction blocks of edge 16");
+static_assert(kSwRPW == 2 && kSwRows < 64, "two rows per wave; loader lanes 1 .. kSwRows");
 static_assert(tile_edge_for_k(3) == kSwT, "same blocks as the tile kernel");
 static_assert(kSwUnroll % kSwRing == 0 && kSwUnroll % kSwPf == 0, "ring slots fixed per group");
 
@@ -84,11 +90,12 @@ struct Sweep3Dev {
 };
 
 struct SwSmem {
-  int32_t ring[kSwRing][kSwNW][kSwRow];    // row w of step s: slot s % 4
+  int32_t ring[kSwRing][kSwNW][kSwRow];    // wave w's lower row at step s: slot s % 4
   int32_t in0[kSwRing][kSwRow];            // the row above the workgroup (wave -1)
+  int32_t h0[kSwRing][kSwNW];              // lane -1 of wave w's upper row
   int32_t junk[64];                        // loader lanes without a halo value write here
   int32_t sub8[kSwSubMax * kSwSubMax];     // substitution matrix << 3
-  alignas(16) uint8_t stage[kSwNW][64][32];  // per lane: two 16-cell runs
+  alignas(16) uint8_t stage[kSwRows][64][32];  // per row and lane: two 16-cell runs
   uint8_t s2[kSwSeqPad + kSwSeqMax + kSwSeqPad];
   int32_t ticket;
 };
@@ -108,12 +115,13 @@ __device__ __forceinline__ void sw_store(int32_t *p, int32_t v) {
 }
 
 // The loader wave.  During step s it writes step s + 1's halo to LDS:
-//   - the row above: in0[s % 4] entry i = cell (B0*kSwNW - 1, B1*64 - 1 + i,
+//   - the row above: in0[s % 4] entry i = cell (B0*kSwRows - 1, B1*64 - 1 + i,
 //     s + 2 - i) = X0[B0-1][B1*64 + s + 1][B1*64 - 1 + i] (element 0 of lane
 //     i; entry 64 is element 1 of lane 0);
-//   - lane -1 of each row w: ring[(s + 1) % 4][w][0] = cell (B0*kSwNW + w,
-//     B1*64 - 1, s + 2 - w) = X1[B1-1][B0*kSwNW + w][s + 2 - w] (element 1
-//     of lane 1 + w);
+//   - lane -1 of row r = 2w + u (wave w's upper row u = 0, lower row u = 1):
+//     cell (B0*kSwRows + r, B1*64 - 1, s + 2 - w) = X1[B1-1][B0*kSwRows + r]
+//     [s + 2 - w] (element 1 of lane 1 + r), to h0[(s + 1) % 4][w] (u = 0) or
+//     ring[(s + 1) % 4][w][0] (u = 1);
 // and issues the loads of step s + kSwPf.  A cell outside the tensor, or
 // without a workgroup before this one, reads -infinity.  Every lane issues
 // both loads every step (an address clamped into its element's window of
@@ -169,12 +177,15 @@ struct SwLoader {
         set(1, sd.x0 + (int64_t)(B0 - 1) * sd.x0_plane +
                    (int64_t)(B1 * kSwLanes + 63) * (sd.n1 + 1) + v1,
             62, sd.n1 + 1, sd.n2, s_first);
-    } else if (lane <= kSwNW) {
-      const int w = lane - 1;
-      const int v0 = B0 * kSwNW + w;
+    } else if (lane <= kSwRows) {
+      const int r = lane - 1;
+      const int w = r / kSwRPW;
+      const int v0 = B0 * kSwRows + r;
 #pragma unroll
       for (int k = 0; k < kSwRing; ++k)
-        dst1[k] = (int32_t)(&sm.ring[(k + 1) & (kSwRing - 1)][w][0] - rbase);
+        dst1[k] = (int32_t)((r % kSwRPW == 0 ? &sm.h0[(k + 1) & (kSwRing - 1)][w]
+                                             : &sm.ring[(k + 1) & (kSwRing - 1)][w][0]) -
+                            rbase);
       if (B1 > 0 && v0 <= sd.n0)
         set(1, sd.x1 + (int64_t)(B1 - 1) * sd.x1_plane + (int64_t)v0 * (sd.n2 + 1),
             w - 2, 1, sd.n2, s_first);
@@ -251,66 +262,84 @@ struct SwLoader {
   }
 };
 
-// One compute wave: row v0 = B0*kSwNW + w, lane j: column v1 = B1*64 + j.
-// kX0: the last row of a workgroup with one below it (stores X0); kX1: a row
-// of a workgroup with one to its right (lane 63 stores X1); kOrigin: wave 0
-// of workgroup (0, 0), whose lane 0 holds the origin.  kEgf: end-gap-free
-// mode (Section 2's reading of free end gaps): every cell with some v_i = 0
-// scores 0 with no decision, and the best far-face cell is reported.
+// One compute wave: rows v0a = B0*kSwRows + 2w (upper) and v0b = v0a + 1
+// (lower), lane j: column v1 = B1*64 + j.  kX0: the workgroup's last row has
+// a workgroup below it (this wave stores X0 from its lower row); kX1: the
+// workgroup has one to its right (lane 63 stores X1); kOrigin: wave 0 of
+// workgroup (0, 0), whose upper row's lane 0 holds the origin.  kEgf:
+// end-gap-free mode (Section 2's reading of free end gaps): every cell with
+// some v_i = 0 scores 0 with no decision, and the best far-face cell is
+// reported.
 template <bool kX0, bool kX1, bool kOrigin, bool kEgf>
 __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B0, int B1, int w,
-                                          int j, bool lane_ok, int r0, int r1, int gap, int tag,
-                                          int total) {
-  const int v0 = B0 * kSwNW + w;
+                                          int j, bool ok_a, bool ok_b, int r0a, int r0b, int r1,
+                                          int gap, int tag, int total, bool cw, int sc, int uc,
+                                          int jc) {
+  const int v0a = B0 * kSwRows + kSwRPW * w;
+  const int v0b = v0a + 1;
   const int v1 = B1 * kSwLanes + j;
   const int g16 = gap * 16;  // (gap * 2 column pairs) << 3
   const int32_t K1 = g16 + 6, K2 = g16 + 5, K4 = g16 + 3;
-  const int32_t p01 = sm.sub8[r0 * kSwSubMax + r1];
-  const int32_t C3 = p01 + g16 + 4, K5 = g16 + 2, K6 = g16 + 1;
+  const int32_t p01a = sm.sub8[r0a * kSwSubMax + r1];
+  const int32_t p01b = sm.sub8[r0b * kSwSubMax + r1];
+  const int32_t C3a = p01a + g16 + 4, C3b = p01b + g16 + 4, K5 = g16 + 2, K6 = g16 + 1;
   // direction bytes: tile (c0, c1, c2), line q0 * 16 + q1, byte q2
-  const int c0 = v0 == 0 ? 0 : (v0 - 1) / kSwT + 1, q0 = v0 == 0 ? 0 : (v0 - 1) % kSwT;
   const int c1 = v1 == 0 ? 0 : (v1 - 1) / kSwT + 1, q1 = v1 == 0 ? 0 : (v1 - 1) % kSwT;
-  uint8_t *const dline =
-      sd.dir + ((int64_t)c0 * sd.ts0 + (int64_t)c1 * sd.ts1) * kSwDbs + (q0 * kSwT + q1) * kSwT;
-  uint8_t *const stage = &sm.stage[w][j][0];
+  const int c0a = v0a == 0 ? 0 : (v0a - 1) / kSwT + 1, q0a = v0a == 0 ? 0 : (v0a - 1) % kSwT;
+  const int c0b = (v0b - 1) / kSwT + 1, q0b = (v0b - 1) % kSwT;
+  uint8_t *const dline_a =
+      sd.dir + ((int64_t)c0a * sd.ts0 + (int64_t)c1 * sd.ts1) * kSwDbs + (q0a * kSwT + q1) * kSwT;
+  uint8_t *const dline_b =
+      sd.dir + ((int64_t)c0b * sd.ts0 + (int64_t)c1 * sd.ts1) * kSwDbs + (q0b * kSwT + q1) * kSwT;
+  uint8_t *const stage_a = &sm.stage[kSwRPW * w][j][0];
+  uint8_t *const stage_b = &sm.stage[kSwRPW * w + 1][j][0];
   const int n2 = sd.n2;
   // rows of the wave above: the loader's in0 for wave 0, else the ring
   const int32_t *const prow = (w == 0 ? &sm.in0[0][0] : &sm.ring[0][w - 1][0]) + j;
   const int pstride = w == 0 ? kSwRow : kSwNW * kSwRow;
-  const int32_t *const sub_r0 = sm.sub8 + r0 * kSwSubMax;
+  const int32_t *const sub_a = sm.sub8 + r0a * kSwSubMax;
+  const int32_t *const sub_b = sm.sub8 + r0b * kSwSubMax;
   const int32_t *const sub_r1 = sm.sub8 + r1 * kSwSubMax;
   const int jw = j + w;
-  // exchange stores: cell (v0, v1, t) of the last row at X0[B0][v1 + t][v1]
-  // (v1 + t = B1*64 + s - w); lane 63's cell at X1[B1][v0][t] (t = s - 63 - w)
+  // exchange stores: cell (v0b, v1, t) of the last row at X0[B0][v1 + t][v1]
+  // (v1 + t = B1*64 + s - w); lane 63's cells at X1[B1][v0][t] (t = s - 63 - w)
   int32_t *const x0b = sd.x0 + (int64_t)B0 * sd.x0_plane +
                        (int64_t)(B1 * kSwLanes - w) * (sd.n1 + 1) + v1;
   const int64_t x0inc = sd.n1 + 1;
-  int32_t *const x1b = sd.x1 + (int64_t)B1 * sd.x1_plane + (int64_t)v0 * (sd.n2 + 1) - (63 + w);
+  int32_t *const x1a = sd.x1 + (int64_t)B1 * sd.x1_plane + (int64_t)v0a * (sd.n2 + 1) - (63 + w);
+  int32_t *const x1b = x1a + (sd.n2 + 1);
   const bool lane63 = j == 63;
-  // end-gap-free: boundary lanes (v0 = 0 or v1 = 0), far lanes (v0 = n0 or
+  // end-gap-free: boundary lanes (some v_i = 0), far lanes (v0 = n0 or
   // v1 = n1; every lane's cell t = n2 is far too), and the row-major index of
-  // the lane's cell t = 0 (below 2^32, checked by the plan's set-up)
-  // the wave's cells t = 0 fall in steps w .. w + 63 and its cells t = n2 in
+  // the lane's cell t = 0 per row (below 2^32, checked by the plan's set-up).
+  // The wave's cells t = 0 fall in steps w .. w + 63 and its cells t = n2 in
   // steps n2 + w .. n2 + w + 63; outside those windows only waves holding
-  // a boundary or far lane test their cells (wave-uniform branches)
-  const bool ebz = v0 == 0 || v1 == 0;
-  const bool efar = v0 == sd.n0 || v1 == sd.n1;
-  const bool wbz = __builtin_amdgcn_ballot_w64(ebz) != 0;
-  const bool wfar = __builtin_amdgcn_ballot_w64(efar) != 0;
-  const uint32_t elin0 =
-      ((uint32_t)v0 * (uint32_t)(sd.n1 + 1) + (uint32_t)v1) * (uint32_t)(sd.n2 + 1);
-  // the lane's best far cell so far: its key (score << 3) and t; among equal
+  // a boundary or far lane test their cells (wave-uniform branches).
+  const bool ebz_a = v0a == 0 || v1 == 0;
+  const bool ebz_b = v1 == 0;
+  const bool efar_a = v0a == sd.n0 || v1 == sd.n1;
+  const bool efar_b = v0b == sd.n0 || v1 == sd.n1;
+  const bool wbz = __builtin_amdgcn_ballot_w64(ebz_a) != 0;
+  const bool wfar = __builtin_amdgcn_ballot_w64(efar_a || efar_b) != 0;
+  const uint32_t elin_a =
+      ((uint32_t)v0a * (uint32_t)(sd.n1 + 1) + (uint32_t)v1) * (uint32_t)(sd.n2 + 1);
+  const uint32_t elin_b = elin_a + (uint32_t)(sd.n1 + 1) * (uint32_t)(sd.n2 + 1);
+  // each row's best far cell so far: its key (score << 3) and t; among equal
   // scores the later t, whose row-major index is larger
-  int32_t eout = INT32_MIN;
-  int et = 0;
+  int32_t eout_a = INT32_MIN, eout_b = INT32_MIN;
+  int et_a = 0, et_b = 0;
 
-  int32_t outp = kNegKey;   // own output of the previous step (cell t - 1)
-  int32_t b5 = kNegKey, b6 = kNegKey, b7 = kNegKey;
-  int32_t hcur = sm.ring[kSwRing - 1][w][0];  // lane -1 at t = -w (step -1)
+  // upper row: own previous output and the neighbours of one step back
+  int32_t outa = kNegKey, b5 = kNegKey, b6 = kNegKey, b7 = kNegKey;
+  // lower row: own previous output and its (v0b, v1 - 1, t - 1)
+  int32_t outb = kNegKey, d6 = kNegKey;
+  int32_t ha = sm.h0[kSwRing - 1][w];         // lane -1 at t = -w (step -1), upper row
+  int32_t hb = sm.ring[kSwRing - 1][w][0];    // and lower row
   // pair scores of the third residue one step ahead (they do not depend on
   // the scores), and its code two steps ahead; s2_j[s] is the residue of t
   const uint8_t *s2_j = sm.s2 + kSwSeqPad - 1 - jw;
-  int32_t p02n = sub_r0[s2_j[0]];
+  int32_t p02an = sub_a[s2_j[0]];
+  int32_t p02bn = sub_b[s2_j[0]];
   int32_t p12n = sub_r1[s2_j[0]];
   int r2n = s2_j[1];
   for (int s0 = 0; s0 < total; s0 += kSwUnroll) {
@@ -318,55 +347,97 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
     for (int i = 0; i < kSwUnroll; ++i) {
       const int s = s0 + i;
       const int t = s - jw;
-      const bool valid = lane_ok && (unsigned)t <= (unsigned)n2;
-      const int32_t p02 = p02n;
+      const bool in_t = (unsigned)t <= (unsigned)n2;
+      const bool valid_a = ok_a && in_t;
+      const bool valid_b = ok_b && in_t;
+      const int32_t p02a = p02an;
+      const int32_t p02b = p02bn;
       const int32_t p12 = p12n;
-      p02n = sub_r0[r2n];
+      p02an = sub_a[r2n];
+      p02bn = sub_b[r2n];
       p12n = sub_r1[r2n];
       r2n = s2_j[s + 2];
-      // neighbours from the row above: (v0-1, v1, t) and (v0-1, v1-1, t)
+      // upper row's neighbours in the row above: (v0a-1, v1, t), (v0a-1, v1-1, t)
       const int32_t b1 = prow[((i - 1) & (kSwRing - 1)) * pstride + 1];
       const int32_t b3 = prow[((i - 2) & (kSwRing - 1)) * pstride];
-      const int32_t hnext = sm.ring[i & (kSwRing - 1)][w][0];
-      // (v0, v1-1, t): lane j-1's previous output; lane 0 takes lane -1's
-      const int32_t b2 = __builtin_amdgcn_update_dpp(hcur, outp, 0x138, 0xF, 0xF, false);
-      const int32_t c1 = b1 + K1;
-      const int32_t c2 = b2 + K2;
-      const int32_t c3 = b3 + C3;
-      const int32_t c4 = outp + K4;
-      const int32_t c5 = b5 + p02 + K5;
-      const int32_t c6 = b6 + p12 + K6;
-      const int32_t c7 = b7 + p01 + (p02 + p12);
-      int32_t best = max(max(max(c1, c2), c3), max(max(max(c4, c5), c6), c7));
+      const int32_t ha_next = sm.h0[i & (kSwRing - 1)][w];
+      const int32_t hb_next = sm.ring[i & (kSwRing - 1)][w][0];
+      // (v0a, v1-1, t) and (v0b, v1-1, t): lane j-1's previous outputs; lane
+      // 0 takes lane -1's
+      const int32_t b2 = __builtin_amdgcn_update_dpp(ha, outa, 0x138, 0xF, 0xF, false);
+      const int32_t d2 = __builtin_amdgcn_update_dpp(hb, outb, 0x138, 0xF, 0xF, false);
+      int32_t best_a;
+      {
+        const int32_t c1 = b1 + K1;
+        const int32_t c2 = b2 + K2;
+        const int32_t c3 = b3 + C3a;
+        const int32_t c4 = outa + K4;
+        const int32_t c5 = b5 + p02a + K5;
+        const int32_t c6 = b6 + p12 + K6;
+        const int32_t c7 = b7 + p01a + (p02a + p12);
+        best_a = max(max(max(c1, c2), c3), max(max(max(c4, c5), c6), c7));
+      }
       // the origin takes key 7: score 0, and the byte decodes to mask 0
       // (end-gap-free: every cell with some v_i = 0)
       if constexpr (kEgf) {
-        if (wbz || (unsigned)(s - w) < 64u) best = (ebz || t == 0) ? 7 : best;
+        if (wbz || (unsigned)(s - w) < 64u) best_a = (ebz_a || t == 0) ? 7 : best_a;
       } else if constexpr (kOrigin) {
-        best = (j == 0 && t == 0) ? 7 : best;
+        best_a = (j == 0 && t == 0) ? 7 : best_a;
       }
-      const int32_t out = valid ? (best & ~7) : kNegKey;
+      const int32_t out_a = valid_a ? (best_a & ~7) : kNegKey;
+      // lower row: its neighbours in the upper row are (v0a, v1, t) = out_a,
+      // (v0a, v1-1, t) = b2, (v0a, v1, t-1) = outa, (v0a, v1-1, t-1) = b6
+      int32_t best_b;
+      {
+        const int32_t c1 = out_a + K1;
+        const int32_t c2 = d2 + K2;
+        const int32_t c3 = b2 + C3b;
+        const int32_t c4 = outb + K4;
+        const int32_t c5 = outa + p02b + K5;
+        const int32_t c6 = d6 + p12 + K6;
+        const int32_t c7 = b6 + p01b + (p02b + p12);
+        // c1 waits for the upper row's output: take it last
+        best_b = max(max(max(max(c4, c2), c3), max(max(c5, c6), c7)), c1);
+      }
+      if constexpr (kEgf) {
+        if (wbz || (unsigned)(s - w) < 64u) best_b = (ebz_b || t == 0) ? 7 : best_b;
+      }
+      const int32_t out_b = valid_b ? (best_b & ~7) : kNegKey;
       if constexpr (kEgf) {
         if (wfar || (unsigned)(s - w - n2) < 64u) {
-          const bool take = valid && (efar ? out >= eout : t == n2);
-          eout = take ? out : eout;
-          et = take ? t : et;
+          const bool take_a = valid_a && (efar_a ? out_a >= eout_a : t == n2);
+          eout_a = take_a ? out_a : eout_a;
+          et_a = take_a ? t : et_a;
+          const bool take_b = valid_b && (efar_b ? out_b >= eout_b : t == n2);
+          eout_b = take_b ? out_b : eout_b;
+          et_b = take_b ? t : et_b;
         }
       }
-      sm.ring[i & (kSwRing - 1)][w][j + 1] = out;
-      // direction byte of cell t at (t - 1) mod 32 (see the flush below)
-      stage[(t - 1) & 31] = (uint8_t)best;
+      sm.ring[i & (kSwRing - 1)][w][j + 1] = out_b;
+      // direction bytes of cell t at (t - 1) mod 32 (see the flush below)
+      stage_a[(t - 1) & 31] = (uint8_t)best_a;
+      stage_b[(t - 1) & 31] = (uint8_t)best_b;
       if constexpr (kX0) {
-        if (valid) sw_store(x0b + (int64_t)s * x0inc, out | tag);
+        if (valid_b) sw_store(x0b + (int64_t)s * x0inc, out_b | tag);
       }
       if constexpr (kX1) {
-        if (valid && lane63) sw_store(x1b + s, out | tag);
+        if (lane63) {
+          if (valid_a) sw_store(x1a + s, out_a | tag);
+          if (valid_b) sw_store(x1b + s, out_b | tag);
+        }
+      }
+      // the score: the corner cell (n0, n1, n2) (wave-uniform test)
+      if (cw && s == sc) {
+        if (j == jc) *sd.score_out = (int64_t)((uc == 0 ? out_a : out_b) >> 3);
       }
       b5 = b1;
       b6 = b2;
       b7 = b3;
-      outp = out;
-      hcur = hnext;
+      outa = out_a;
+      d6 = d2;
+      outb = out_b;
+      ha = ha_next;
+      hb = hb_next;
       sw_barrier();
     }
     // ---- direction runs completed in the last 16 steps ----
@@ -375,25 +446,34 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
     // 16 cells, so a run is stored before any later cell reaches its half;
     // cells past n2 only touch the tail of the last run (bytes of no cell)
     // or halves that are never stored again.
-    if (lane_ok) {
-      const int tf = s0 + kSwUnroll - 1 - jw;
-      if (tf >= 0 && tf < 16) dline[0] = stage[31];  // cell t = 0 (its own block)
-      const int c = tf >> 4;                         // run c: cells 16c - 15 .. 16c
-      if (c >= 1 && 16 * c <= n2)
-        *reinterpret_cast<uint4 *>(dline + (int64_t)c * kSwDbs) =
-            *reinterpret_cast<const uint4 *>(stage + ((c - 1) & 1) * 16);
-      const int cl = (n2 >> 4) + 1;                  // the last, partial run
-      if ((n2 & 15) != 0 && tf >= n2 && tf - 15 <= n2)
-        *reinterpret_cast<uint4 *>(dline + (int64_t)cl * kSwDbs) =
-            *reinterpret_cast<const uint4 *>(stage + ((cl - 1) & 1) * 16);
+    const int tf = s0 + kSwUnroll - 1 - jw;
+    const int c = tf >> 4;                         // run c: cells 16c - 15 .. 16c
+    const int cl = (n2 >> 4) + 1;                  // the last, partial run
+#pragma unroll
+    for (int u = 0; u < kSwRPW; ++u) {
+      if (u == 0 ? ok_a : ok_b) {
+        uint8_t *const dline = u == 0 ? dline_a : dline_b;
+        const uint8_t *const stage = u == 0 ? stage_a : stage_b;
+        if (tf >= 0 && tf < 16) dline[0] = stage[31];  // cell t = 0 (its own block)
+        if (c >= 1 && 16 * c <= n2)
+          *reinterpret_cast<uint4 *>(dline + (int64_t)c * kSwDbs) =
+              *reinterpret_cast<const uint4 *>(stage + ((c - 1) & 1) * 16);
+        if ((n2 & 15) != 0 && tf >= n2 && tf - 15 <= n2)
+          *reinterpret_cast<uint4 *>(dline + (int64_t)cl * kSwDbs) =
+              *reinterpret_cast<const uint4 *>(stage + ((cl - 1) & 1) * 16);
+      }
     }
   }
   if constexpr (kEgf) {
     // the lane's far-face key (score << 32 | row-major index), the wave's
     // best, then one atomic per wave
-    int64_t ekey = eout == INT32_MIN
-                       ? INT64_MIN
-                       : ((int64_t)(eout >> 3) << 32) | (int64_t)(elin0 + (uint32_t)et);
+    const int64_t ka = eout_a == INT32_MIN
+                           ? INT64_MIN
+                           : ((int64_t)(eout_a >> 3) << 32) | (int64_t)(elin_a + (uint32_t)et_a);
+    const int64_t kb = eout_b == INT32_MIN
+                           ? INT64_MIN
+                           : ((int64_t)(eout_b >> 3) << 32) | (int64_t)(elin_b + (uint32_t)et_b);
+    int64_t ekey = ka > kb ? ka : kb;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const int64_t o = __shfl_xor(ekey, d, 64);
@@ -403,24 +483,27 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
   }
 }
 
-// The row's variant: exchange stores (x0, x1) and the origin.
+// The wave's variant: exchange stores (x0, x1) and the origin.
 template <bool kEgf>
 __device__ __forceinline__ void sweep_rows(const Sweep3Dev &sd, SwSmem &sm, int B0, int B1,
-                                           int w, int j, bool lane_ok, int r0, int r1, int gap,
-                                           int tag, int total, bool x0, bool x1) {
+                                           int w, int j, bool ok_a, bool ok_b, int r0a, int r0b,
+                                           int r1, int gap, int tag, int total, bool x0, bool x1,
+                                           bool cw, int sc, int uc, int jc) {
+#define MSA_SW_ARGS sd, sm, B0, B1, w, j, ok_a, ok_b, r0a, r0b, r1, gap, tag, total, cw, sc, uc, jc
   if (B0 == 0 && B1 == 0 && w == 0) {
     if (x1)
-      sweep_row<false, true, true, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+      sweep_row<false, true, true, kEgf>(MSA_SW_ARGS);
     else
-      sweep_row<false, false, true, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+      sweep_row<false, false, true, kEgf>(MSA_SW_ARGS);
   } else if (x0 && x1)
-    sweep_row<true, true, false, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+    sweep_row<true, true, false, kEgf>(MSA_SW_ARGS);
   else if (x0)
-    sweep_row<true, false, false, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+    sweep_row<true, false, false, kEgf>(MSA_SW_ARGS);
   else if (x1)
-    sweep_row<false, true, false, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+    sweep_row<false, true, false, kEgf>(MSA_SW_ARGS);
   else
-    sweep_row<false, false, false, kEgf>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total);
+    sweep_row<false, false, false, kEgf>(MSA_SW_ARGS);
+#undef MSA_SW_ARGS
 }
 
 }  // namespace
@@ -450,6 +533,7 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
   // the rings before step 0 hold cells t < 0: -infinity
   for (int e = tid; e < kSwRing * kSwNW * kSwRow; e += kSwThreads)
     (&sm.ring[0][0][0])[e] = kNegKey;
+  for (int e = tid; e < kSwRing * kSwNW; e += kSwThreads) (&sm.h0[0][0])[e] = kNegKey;
   sw_barrier();
   const int ticket = __builtin_amdgcn_readfirstlane(sm.ticket);
   // A ticket past the grid means the counter was not reset since the last
@@ -475,10 +559,6 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
     // ---------------- loader wave ----------------
     if (bad) atomicCAS(&ctrl->status, 0, -1);
     SwLoader ld(sd, sm, B0, B1, j, reinterpret_cast<const int32_t *>(ctrl), -2);
-    // the score: the corner's cell t = n2 is lane jc of wave wc at step sc
-    const bool cblock = B0 == sd.n0 / kSwNW && B1 == sd.n1 / kSwLanes;
-    const int wc = sd.n0 % kSwNW, jc = sd.n1 % kSwLanes;
-    const int sc = sd.n2 + jc + wc;
 #ifdef MSA_TRACE
     const int64_t t0 = (int64_t)wall_clock64();
 #endif
@@ -505,8 +585,6 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
         const int s = s0 + i;
         // during step s: step s + 1's halo (loaded kSwPf steps ago)
         ld.finish(s, kSwPf, q[i % kSwPf], tag, sm, j, ctrl, nspin);
-        if (cblock && s == sc + 1)
-          *sd.score_out = (int64_t)(sm.ring[sc & (kSwRing - 1)][wc][jc + 1] >> 3);
         sw_barrier();
         ld.issue(q[i % kSwPf]);  // step s + kSwPf
       }
@@ -528,23 +606,35 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
 
   // ---------------- compute waves ----------------
   const int w = wave;
-  const int v0 = B0 * kSwNW + w;
+  const int v0a = B0 * kSwRows + kSwRPW * w;
+  const int v0b = v0a + 1;
   const int v1 = B1 * kSwLanes + j;
-  const bool row_ok = v0 <= sd.n0;
-  const bool lane_ok = row_ok && v1 <= sd.n1;
-  int r0 = (row_ok && v0 >= 1) ? (int)sd.s0[v0 - 1] : 0;
-  int r1 = (lane_ok && v1 >= 1) ? (int)sd.s1[v1 - 1] : 0;
-  bad = bad || r0 >= alpha || r1 >= alpha;
+  const bool row_a = v0a <= sd.n0, row_b = v0b <= sd.n0;
+  const bool col_ok = v1 <= sd.n1;
+  int r0a = (row_a && v0a >= 1) ? (int)sd.s0[v0a - 1] : 0;
+  int r0b = row_b ? (int)sd.s0[v0b - 1] : 0;
+  int r1 = (row_a && col_ok && v1 >= 1) ? (int)sd.s1[v1 - 1] : 0;
+  bad = bad || r0a >= alpha || r0b >= alpha || r1 >= alpha;
   if (bad) atomicCAS(&ctrl->status, 0, -1);
-  r0 = __builtin_amdgcn_readfirstlane(r0 >= alpha ? 0 : r0);
+  r0a = __builtin_amdgcn_readfirstlane(r0a >= alpha ? 0 : r0a);
+  r0b = __builtin_amdgcn_readfirstlane(r0b >= alpha ? 0 : r0b);
   r1 = r1 >= alpha ? 0 : r1;
-  const bool x0 = w == kSwNW - 1 && B0 < sd.nb0 - 1 && row_ok;
-  const bool x1 = B1 < sd.nb1 - 1 && row_ok;
+  const bool x0 = w == kSwNW - 1 && B0 < sd.nb0 - 1 && row_b;
+  const bool x1 = B1 < sd.nb1 - 1 && row_a;
+  // the score: the corner cell's t = n2 is row uc of wave wc, lane jc, at
+  // step sc of workgroup (n0 / kSwRows, n1 / 64)
+  const int rc = sd.n0 % kSwRows;
+  const bool cw = B0 == sd.n0 / kSwRows && B1 == sd.n1 / kSwLanes && w == rc / kSwRPW;
+  const int jc = sd.n1 % kSwLanes;
+  const int sc = sd.n2 + jc + w;
+  const int uc = rc % kSwRPW;
   sw_barrier();  // the loader's halo of steps -1 and 0 is in LDS
   if (sd.egf)
-    sweep_rows<true>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total, x0, x1);
+    sweep_rows<true>(sd, sm, B0, B1, w, j, row_a && col_ok, row_b && col_ok, r0a, r0b, r1, gap,
+                     tag, total, x0, x1, cw, sc, uc, jc);
   else
-    sweep_rows<false>(sd, sm, B0, B1, w, j, lane_ok, r0, r1, gap, tag, total, x0, x1);
+    sweep_rows<false>(sd, sm, B0, B1, w, j, row_a && col_ok, row_b && col_ok, r0a, r0b, r1, gap,
+                      tag, total, x0, x1, cw, sc, uc, jc);
 }
 
 int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, int32_t flags,
