@@ -67,7 +67,7 @@ constexpr int kSwDbs = kSwT * kSwT * kSwT;
 constexpr int64_t kSwWaitTicks = 200000000;  // 2 s of waiting (WaitClock ticks)
 
 static_assert(kSwDbs == 4096, "direction blocks of edge 16");
-static_assert(kSwRPW == 2 && kSwRows < 64, "two rows per wave; loader lanes 1 .. kSwRows");
+static_assert(kSwRPW >= 2 && kSwRows < 64, "loader lanes 1 .. kSwRows");
 static_assert(tile_edge_for_k(3) == kSwT, "same blocks as the tile kernel");
 static_assert(kSwUnroll % kSwRing == 0 && kSwUnroll % kSwPf == 0, "ring slots fixed per group");
 
@@ -92,7 +92,7 @@ struct Sweep3Dev {
 struct SwSmem {
   int32_t ring[kSwRing][kSwNW][kSwRow];    // wave w's lower row at step s: slot s % 4
   int32_t in0[kSwRing][kSwRow];            // the row above the workgroup (wave -1)
-  int32_t h0[kSwRing][kSwNW];              // lane -1 of wave w's upper row
+  int32_t h0[kSwRing][kSwNW][kSwRPW - 1];  // lane -1 of wave w's rows above its last
   int32_t junk[64];                        // loader lanes without a halo value write here
   int32_t sub8[kSwSubMax * kSwSubMax];     // substitution matrix << 3
   alignas(16) uint8_t stage[kSwRows][64][32];  // per row and lane: two 16-cell runs
@@ -183,8 +183,9 @@ struct SwLoader {
       const int v0 = B0 * kSwRows + r;
 #pragma unroll
       for (int k = 0; k < kSwRing; ++k)
-        dst1[k] = (int32_t)((r % kSwRPW == 0 ? &sm.h0[(k + 1) & (kSwRing - 1)][w]
-                                             : &sm.ring[(k + 1) & (kSwRing - 1)][w][0]) -
+        dst1[k] = (int32_t)((r % kSwRPW < kSwRPW - 1
+                                 ? &sm.h0[(k + 1) & (kSwRing - 1)][w][r % kSwRPW]
+                                 : &sm.ring[(k + 1) & (kSwRing - 1)][w][0]) -
                             rbase);
       if (B1 > 0 && v0 <= sd.n0)
         set(1, sd.x1 + (int64_t)(B1 - 1) * sd.x1_plane + (int64_t)v0 * (sd.n2 + 1),
@@ -262,84 +263,96 @@ struct SwLoader {
   }
 };
 
-// One compute wave: rows v0a = B0*kSwRows + 2w (upper) and v0b = v0a + 1
-// (lower), lane j: column v1 = B1*64 + j.  kX0: the workgroup's last row has
-// a workgroup below it (this wave stores X0 from its lower row); kX1: the
-// workgroup has one to its right (lane 63 stores X1); kOrigin: wave 0 of
-// workgroup (0, 0), whose upper row's lane 0 holds the origin.  kEgf:
+// One compute wave: rows v0 = B0*kSwRows + kSwRPW*w + u, u = 0 .. kSwRPW - 1
+// (top to bottom), lane j: column v1 = B1*64 + j.  kX0: the workgroup's last
+// row has a workgroup below it (this wave stores X0 from its last row); kX1:
+// the workgroup has one to its right (lane 63 stores X1); kOrigin: wave 0 of
+// workgroup (0, 0), whose top row's lane 0 holds the origin.  kEgf:
 // end-gap-free mode (Section 2's reading of free end gaps): every cell with
 // some v_i = 0 scores 0 with no decision, and the best far-face cell is
 // reported.
 template <bool kX0, bool kX1, bool kOrigin, bool kEgf>
 __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B0, int B1, int w,
-                                          int j, bool ok_a, bool ok_b, int r0a, int r0b, int r1,
-                                          int gap, int tag, int total, bool cw, int sc, int uc,
-                                          int jc) {
-  const int v0a = B0 * kSwRows + kSwRPW * w;
-  const int v0b = v0a + 1;
+                                          int j, const bool (&ok)[kSwRPW],
+                                          const int (&r0)[kSwRPW], int r1, int gap, int tag,
+                                          int total, bool cw, int sc, int uc, int jc) {
+  constexpr int R = kSwRPW;
+  const int v0top = B0 * kSwRows + R * w;
   const int v1 = B1 * kSwLanes + j;
   const int g16 = gap * 16;  // (gap * 2 column pairs) << 3
-  const int32_t K1 = g16 + 6, K2 = g16 + 5, K4 = g16 + 3;
-  const int32_t p01a = sm.sub8[r0a * kSwSubMax + r1];
-  const int32_t p01b = sm.sub8[r0b * kSwSubMax + r1];
-  const int32_t C3a = p01a + g16 + 4, C3b = p01b + g16 + 4, K5 = g16 + 2, K6 = g16 + 1;
-  // direction bytes: tile (c0, c1, c2), line q0 * 16 + q1, byte q2
-  const int c1 = v1 == 0 ? 0 : (v1 - 1) / kSwT + 1, q1 = v1 == 0 ? 0 : (v1 - 1) % kSwT;
-  const int c0a = v0a == 0 ? 0 : (v0a - 1) / kSwT + 1, q0a = v0a == 0 ? 0 : (v0a - 1) % kSwT;
-  const int c0b = (v0b - 1) / kSwT + 1, q0b = (v0b - 1) % kSwT;
-  uint8_t *const dline_a =
-      sd.dir + ((int64_t)c0a * sd.ts0 + (int64_t)c1 * sd.ts1) * kSwDbs + (q0a * kSwT + q1) * kSwT;
-  uint8_t *const dline_b =
-      sd.dir + ((int64_t)c0b * sd.ts0 + (int64_t)c1 * sd.ts1) * kSwDbs + (q0b * kSwT + q1) * kSwT;
-  uint8_t *const stage_a = &sm.stage[kSwRPW * w][j][0];
-  uint8_t *const stage_b = &sm.stage[kSwRPW * w + 1][j][0];
+  const int32_t K1 = g16 + 6, K2 = g16 + 5, K4 = g16 + 3, K5 = g16 + 2, K6 = g16 + 1;
   const int n2 = sd.n2;
+  const int c1 = v1 == 0 ? 0 : (v1 - 1) / kSwT + 1, q1 = v1 == 0 ? 0 : (v1 - 1) % kSwT;
+  int32_t p01[R], C3[R];
+  const int32_t *sub0[R];
+  uint8_t *dline[R];
+  uint8_t *stage[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int v0 = v0top + u;
+    p01[u] = sm.sub8[r0[u] * kSwSubMax + r1];
+    C3[u] = p01[u] + g16 + 4;
+    sub0[u] = sm.sub8 + r0[u] * kSwSubMax;
+    // direction bytes: tile (c0, c1, c2), line q0 * 16 + q1, byte q2
+    const int c0 = v0 == 0 ? 0 : (v0 - 1) / kSwT + 1, q0 = v0 == 0 ? 0 : (v0 - 1) % kSwT;
+    dline[u] =
+        sd.dir + ((int64_t)c0 * sd.ts0 + (int64_t)c1 * sd.ts1) * kSwDbs + (q0 * kSwT + q1) * kSwT;
+    stage[u] = &sm.stage[R * w + u][j][0];
+  }
   // rows of the wave above: the loader's in0 for wave 0, else the ring
   const int32_t *const prow = (w == 0 ? &sm.in0[0][0] : &sm.ring[0][w - 1][0]) + j;
   const int pstride = w == 0 ? kSwRow : kSwNW * kSwRow;
-  const int32_t *const sub_a = sm.sub8 + r0a * kSwSubMax;
-  const int32_t *const sub_b = sm.sub8 + r0b * kSwSubMax;
   const int32_t *const sub_r1 = sm.sub8 + r1 * kSwSubMax;
   const int jw = j + w;
-  // exchange stores: cell (v0b, v1, t) of the last row at X0[B0][v1 + t][v1]
+  // exchange stores: cell (v0, v1, t) of the last row at X0[B0][v1 + t][v1]
   // (v1 + t = B1*64 + s - w); lane 63's cells at X1[B1][v0][t] (t = s - 63 - w)
   int32_t *const x0b = sd.x0 + (int64_t)B0 * sd.x0_plane +
                        (int64_t)(B1 * kSwLanes - w) * (sd.n1 + 1) + v1;
   const int64_t x0inc = sd.n1 + 1;
-  int32_t *const x1a = sd.x1 + (int64_t)B1 * sd.x1_plane + (int64_t)v0a * (sd.n2 + 1) - (63 + w);
-  int32_t *const x1b = x1a + (sd.n2 + 1);
+  int32_t *const x1t = sd.x1 + (int64_t)B1 * sd.x1_plane + (int64_t)v0top * (sd.n2 + 1) - (63 + w);
   const bool lane63 = j == 63;
-  // end-gap-free: boundary lanes (some v_i = 0), far lanes (v0 = n0 or
+  // end-gap-free: boundary cells (some v_i = 0), far lanes (v0 = n0 or
   // v1 = n1; every lane's cell t = n2 is far too), and the row-major index of
-  // the lane's cell t = 0 per row (below 2^32, checked by the plan's set-up).
-  // The wave's cells t = 0 fall in steps w .. w + 63 and its cells t = n2 in
-  // steps n2 + w .. n2 + w + 63; outside those windows only waves holding
-  // a boundary or far lane test their cells (wave-uniform branches).
-  const bool ebz_a = v0a == 0 || v1 == 0;
-  const bool ebz_b = v1 == 0;
-  const bool efar_a = v0a == sd.n0 || v1 == sd.n1;
-  const bool efar_b = v0b == sd.n0 || v1 == sd.n1;
-  const bool wbz = __builtin_amdgcn_ballot_w64(ebz_a) != 0;
-  const bool wfar = __builtin_amdgcn_ballot_w64(efar_a || efar_b) != 0;
-  const uint32_t elin_a =
-      ((uint32_t)v0a * (uint32_t)(sd.n1 + 1) + (uint32_t)v1) * (uint32_t)(sd.n2 + 1);
-  const uint32_t elin_b = elin_a + (uint32_t)(sd.n1 + 1) * (uint32_t)(sd.n2 + 1);
-  // each row's best far cell so far: its key (score << 3) and t; among equal
-  // scores the later t, whose row-major index is larger
-  int32_t eout_a = INT32_MIN, eout_b = INT32_MIN;
-  int et_a = 0, et_b = 0;
+  // each row's cell t = 0 (below 2^32, checked by the plan's set-up).  The
+  // wave's cells t = 0 fall in steps w .. w + 63 and its cells t = n2 in
+  // steps n2 + w .. n2 + w + 63; outside those windows only waves holding a
+  // boundary or far lane test their cells (wave-uniform branches).
+  bool ebz[R], efar[R];
+  bool anyfar = false;
+  uint32_t elin[R];
+  int32_t eout[R];
+  int et[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int v0 = v0top + u;
+    ebz[u] = v0 == 0 || v1 == 0;
+    efar[u] = v0 == sd.n0 || v1 == sd.n1;
+    anyfar = anyfar || efar[u];
+    elin[u] = ((uint32_t)v0 * (uint32_t)(sd.n1 + 1) + (uint32_t)v1) * (uint32_t)(sd.n2 + 1);
+    // the row's best far cell so far: its key (score << 3) and t; among equal
+    // scores the later t, whose row-major index is larger
+    eout[u] = INT32_MIN;
+    et[u] = 0;
+  }
+  const bool wbz = __builtin_amdgcn_ballot_w64(ebz[0]) != 0;  // (ebz[u > 0] implies ebz[0])
+  const bool wfar = __builtin_amdgcn_ballot_w64(anyfar) != 0;
 
-  // upper row: own previous output and the neighbours of one step back
-  int32_t outa = kNegKey, b5 = kNegKey, b6 = kNegKey, b7 = kNegKey;
-  // lower row: own previous output and its (v0b, v1 - 1, t - 1)
-  int32_t outb = kNegKey, d6 = kNegKey;
-  int32_t ha = sm.h0[kSwRing - 1][w];         // lane -1 at t = -w (step -1), upper row
-  int32_t hb = sm.ring[kSwRing - 1][w][0];    // and lower row
+  // per row: own previous output, lane -1's value, and (v0, v1 - 1, t - 1);
+  // the top row also keeps its other neighbours of one step back
+  int32_t outp[R], hl[R], l6[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    outp[u] = kNegKey;
+    l6[u] = kNegKey;
+    hl[u] = u < R - 1 ? sm.h0[kSwRing - 1][w][u] : sm.ring[kSwRing - 1][w][0];
+  }
+  int32_t b5 = kNegKey, b7 = kNegKey;
   // pair scores of the third residue one step ahead (they do not depend on
   // the scores), and its code two steps ahead; s2_j[s] is the residue of t
   const uint8_t *s2_j = sm.s2 + kSwSeqPad - 1 - jw;
-  int32_t p02an = sub_a[s2_j[0]];
-  int32_t p02bn = sub_b[s2_j[0]];
+  int32_t p02n[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) p02n[u] = sub0[u][s2_j[0]];
   int32_t p12n = sub_r1[s2_j[0]];
   int r2n = s2_j[1];
   for (int s0 = 0; s0 < total; s0 += kSwUnroll) {
@@ -348,96 +361,94 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
       const int s = s0 + i;
       const int t = s - jw;
       const bool in_t = (unsigned)t <= (unsigned)n2;
-      const bool valid_a = ok_a && in_t;
-      const bool valid_b = ok_b && in_t;
-      const int32_t p02a = p02an;
-      const int32_t p02b = p02bn;
+      int32_t p02[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        p02[u] = p02n[u];
+        p02n[u] = sub0[u][r2n];
+      }
       const int32_t p12 = p12n;
-      p02an = sub_a[r2n];
-      p02bn = sub_b[r2n];
       p12n = sub_r1[r2n];
       r2n = s2_j[s + 2];
-      // upper row's neighbours in the row above: (v0a-1, v1, t), (v0a-1, v1-1, t)
+      // the top row's neighbours in the row above: (v0-1, v1, t), (v0-1, v1-1, t)
       const int32_t b1 = prow[((i - 1) & (kSwRing - 1)) * pstride + 1];
       const int32_t b3 = prow[((i - 2) & (kSwRing - 1)) * pstride];
-      const int32_t ha_next = sm.h0[i & (kSwRing - 1)][w];
-      const int32_t hb_next = sm.ring[i & (kSwRing - 1)][w][0];
-      // (v0a, v1-1, t) and (v0b, v1-1, t): lane j-1's previous outputs; lane
-      // 0 takes lane -1's
-      const int32_t b2 = __builtin_amdgcn_update_dpp(ha, outa, 0x138, 0xF, 0xF, false);
-      const int32_t d2 = __builtin_amdgcn_update_dpp(hb, outb, 0x138, 0xF, 0xF, false);
-      int32_t best_a;
-      {
-        const int32_t c1 = b1 + K1;
-        const int32_t c2 = b2 + K2;
-        const int32_t c3 = b3 + C3a;
-        const int32_t c4 = outa + K4;
-        const int32_t c5 = b5 + p02a + K5;
-        const int32_t c6 = b6 + p12 + K6;
-        const int32_t c7 = b7 + p01a + (p02a + p12);
-        best_a = max(max(max(c1, c2), c3), max(max(max(c4, c5), c6), c7));
+      int32_t hnext[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+        hnext[u] = u < R - 1 ? sm.h0[i & (kSwRing - 1)][w][u] : sm.ring[i & (kSwRing - 1)][w][0];
+      // (v0, v1-1, t) per row: lane j-1's previous output; lane 0 takes lane -1's
+      int32_t l2[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+        l2[u] = __builtin_amdgcn_update_dpp(hl[u], outp[u], 0x138, 0xF, 0xF, false);
+      int32_t best[R], out[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        // neighbours in the row above: (v0-1, v1, t), (v0-1, v1-1, t),
+        // (v0-1, v1, t-1), (v0-1, v1-1, t-1); below the top row they are the
+        // row above's values of this step, from registers
+        const int32_t a1 = u == 0 ? b1 : out[u - 1];
+        const int32_t a3 = u == 0 ? b3 : l2[u - 1];
+        const int32_t a5 = u == 0 ? b5 : outp[u - 1];
+        const int32_t a7 = u == 0 ? b7 : l6[u - 1];
+        const int32_t c2 = l2[u] + K2;
+        const int32_t c3 = a3 + C3[u];
+        const int32_t c4 = outp[u] + K4;
+        const int32_t c5 = a5 + p02[u] + K5;
+        const int32_t c6 = l6[u] + p12 + K6;
+        const int32_t c7 = a7 + p01[u] + (p02[u] + p12);
+        // c1 waits for the row above's output (below the top row): take it last
+        int32_t bst = max(max(max(max(c4, c2), c3), max(max(c5, c6), c7)), a1 + K1);
+        // the origin takes key 7: score 0, and the byte decodes to mask 0
+        // (end-gap-free: every cell with some v_i = 0)
+        if constexpr (kEgf) {
+          if (wbz || (unsigned)(s - w) < 64u) bst = (ebz[u] || t == 0) ? 7 : bst;
+        } else if constexpr (kOrigin) {
+          if (u == 0) bst = (j == 0 && t == 0) ? 7 : bst;
+        }
+        best[u] = bst;
+        out[u] = (ok[u] && in_t) ? (bst & ~7) : kNegKey;
       }
-      // the origin takes key 7: score 0, and the byte decodes to mask 0
-      // (end-gap-free: every cell with some v_i = 0)
-      if constexpr (kEgf) {
-        if (wbz || (unsigned)(s - w) < 64u) best_a = (ebz_a || t == 0) ? 7 : best_a;
-      } else if constexpr (kOrigin) {
-        best_a = (j == 0 && t == 0) ? 7 : best_a;
-      }
-      const int32_t out_a = valid_a ? (best_a & ~7) : kNegKey;
-      // lower row: its neighbours in the upper row are (v0a, v1, t) = out_a,
-      // (v0a, v1-1, t) = b2, (v0a, v1, t-1) = outa, (v0a, v1-1, t-1) = b6
-      int32_t best_b;
-      {
-        const int32_t c1 = out_a + K1;
-        const int32_t c2 = d2 + K2;
-        const int32_t c3 = b2 + C3b;
-        const int32_t c4 = outb + K4;
-        const int32_t c5 = outa + p02b + K5;
-        const int32_t c6 = d6 + p12 + K6;
-        const int32_t c7 = b6 + p01b + (p02b + p12);
-        // c1 waits for the upper row's output: take it last
-        best_b = max(max(max(max(c4, c2), c3), max(max(c5, c6), c7)), c1);
-      }
-      if constexpr (kEgf) {
-        if (wbz || (unsigned)(s - w) < 64u) best_b = (ebz_b || t == 0) ? 7 : best_b;
-      }
-      const int32_t out_b = valid_b ? (best_b & ~7) : kNegKey;
       if constexpr (kEgf) {
         if (wfar || (unsigned)(s - w - n2) < 64u) {
-          const bool take_a = valid_a && (efar_a ? out_a >= eout_a : t == n2);
-          eout_a = take_a ? out_a : eout_a;
-          et_a = take_a ? t : et_a;
-          const bool take_b = valid_b && (efar_b ? out_b >= eout_b : t == n2);
-          eout_b = take_b ? out_b : eout_b;
-          et_b = take_b ? t : et_b;
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            const bool take = ok[u] && in_t && (efar[u] ? out[u] >= eout[u] : t == n2);
+            eout[u] = take ? out[u] : eout[u];
+            et[u] = take ? t : et[u];
+          }
         }
       }
-      sm.ring[i & (kSwRing - 1)][w][j + 1] = out_b;
+      sm.ring[i & (kSwRing - 1)][w][j + 1] = out[R - 1];
       // direction bytes of cell t at (t - 1) mod 32 (see the flush below)
-      stage_a[(t - 1) & 31] = (uint8_t)best_a;
-      stage_b[(t - 1) & 31] = (uint8_t)best_b;
+#pragma unroll
+      for (int u = 0; u < R; ++u) stage[u][(t - 1) & 31] = (uint8_t)best[u];
       if constexpr (kX0) {
-        if (valid_b) sw_store(x0b + (int64_t)s * x0inc, out_b | tag);
+        if (ok[R - 1] && in_t) sw_store(x0b + (int64_t)s * x0inc, out[R - 1] | tag);
       }
       if constexpr (kX1) {
         if (lane63) {
-          if (valid_a) sw_store(x1a + s, out_a | tag);
-          if (valid_b) sw_store(x1b + s, out_b | tag);
+#pragma unroll
+          for (int u = 0; u < R; ++u)
+            if (ok[u] && in_t) sw_store(x1t + (int64_t)u * (sd.n2 + 1) + s, out[u] | tag);
         }
       }
       // the score: the corner cell (n0, n1, n2) (wave-uniform test)
       if (cw && s == sc) {
-        if (j == jc) *sd.score_out = (int64_t)((uc == 0 ? out_a : out_b) >> 3);
+        int32_t o = out[0];
+#pragma unroll
+        for (int u = 1; u < R; ++u) o = uc == u ? out[u] : o;
+        if (j == jc) *sd.score_out = (int64_t)(o >> 3);
       }
       b5 = b1;
-      b6 = b2;
       b7 = b3;
-      outa = out_a;
-      d6 = d2;
-      outb = out_b;
-      ha = ha_next;
-      hb = hb_next;
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        l6[u] = l2[u];
+        outp[u] = out[u];
+        hl[u] = hnext[u];
+      }
       sw_barrier();
     }
     // ---- direction runs completed in the last 16 steps ----
@@ -450,30 +461,29 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
     const int c = tf >> 4;                         // run c: cells 16c - 15 .. 16c
     const int cl = (n2 >> 4) + 1;                  // the last, partial run
 #pragma unroll
-    for (int u = 0; u < kSwRPW; ++u) {
-      if (u == 0 ? ok_a : ok_b) {
-        uint8_t *const dline = u == 0 ? dline_a : dline_b;
-        const uint8_t *const stage = u == 0 ? stage_a : stage_b;
-        if (tf >= 0 && tf < 16) dline[0] = stage[31];  // cell t = 0 (its own block)
+    for (int u = 0; u < R; ++u) {
+      if (ok[u]) {
+        if (tf >= 0 && tf < 16) dline[u][0] = stage[u][31];  // cell t = 0 (its own block)
         if (c >= 1 && 16 * c <= n2)
-          *reinterpret_cast<uint4 *>(dline + (int64_t)c * kSwDbs) =
-              *reinterpret_cast<const uint4 *>(stage + ((c - 1) & 1) * 16);
+          *reinterpret_cast<uint4 *>(dline[u] + (int64_t)c * kSwDbs) =
+              *reinterpret_cast<const uint4 *>(stage[u] + ((c - 1) & 1) * 16);
         if ((n2 & 15) != 0 && tf >= n2 && tf - 15 <= n2)
-          *reinterpret_cast<uint4 *>(dline + (int64_t)cl * kSwDbs) =
-              *reinterpret_cast<const uint4 *>(stage + ((cl - 1) & 1) * 16);
+          *reinterpret_cast<uint4 *>(dline[u] + (int64_t)cl * kSwDbs) =
+              *reinterpret_cast<const uint4 *>(stage[u] + ((cl - 1) & 1) * 16);
       }
     }
   }
   if constexpr (kEgf) {
     // the lane's far-face key (score << 32 | row-major index), the wave's
     // best, then one atomic per wave
-    const int64_t ka = eout_a == INT32_MIN
-                           ? INT64_MIN
-                           : ((int64_t)(eout_a >> 3) << 32) | (int64_t)(elin_a + (uint32_t)et_a);
-    const int64_t kb = eout_b == INT32_MIN
-                           ? INT64_MIN
-                           : ((int64_t)(eout_b >> 3) << 32) | (int64_t)(elin_b + (uint32_t)et_b);
-    int64_t ekey = ka > kb ? ka : kb;
+    int64_t ekey = INT64_MIN;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t k = eout[u] == INT32_MIN
+                            ? INT64_MIN
+                            : ((int64_t)(eout[u] >> 3) << 32) | (int64_t)(elin[u] + (uint32_t)et[u]);
+      ekey = k > ekey ? k : ekey;
+    }
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const int64_t o = __shfl_xor(ekey, d, 64);
@@ -486,10 +496,11 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
 // The wave's variant: exchange stores (x0, x1) and the origin.
 template <bool kEgf>
 __device__ __forceinline__ void sweep_rows(const Sweep3Dev &sd, SwSmem &sm, int B0, int B1,
-                                           int w, int j, bool ok_a, bool ok_b, int r0a, int r0b,
-                                           int r1, int gap, int tag, int total, bool x0, bool x1,
-                                           bool cw, int sc, int uc, int jc) {
-#define MSA_SW_ARGS sd, sm, B0, B1, w, j, ok_a, ok_b, r0a, r0b, r1, gap, tag, total, cw, sc, uc, jc
+                                           int w, int j, const bool (&ok)[kSwRPW],
+                                           const int (&r0)[kSwRPW], int r1, int gap, int tag,
+                                           int total, bool x0, bool x1, bool cw, int sc, int uc,
+                                           int jc) {
+#define MSA_SW_ARGS sd, sm, B0, B1, w, j, ok, r0, r1, gap, tag, total, cw, sc, uc, jc
   if (B0 == 0 && B1 == 0 && w == 0) {
     if (x1)
       sweep_row<false, true, true, kEgf>(MSA_SW_ARGS);
@@ -533,7 +544,8 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
   // the rings before step 0 hold cells t < 0: -infinity
   for (int e = tid; e < kSwRing * kSwNW * kSwRow; e += kSwThreads)
     (&sm.ring[0][0][0])[e] = kNegKey;
-  for (int e = tid; e < kSwRing * kSwNW; e += kSwThreads) (&sm.h0[0][0])[e] = kNegKey;
+  for (int e = tid; e < kSwRing * kSwNW * (kSwRPW - 1); e += kSwThreads)
+    (&sm.h0[0][0][0])[e] = kNegKey;
   sw_barrier();
   const int ticket = __builtin_amdgcn_readfirstlane(sm.ticket);
   // A ticket past the grid means the counter was not reset since the last
@@ -606,21 +618,26 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
 
   // ---------------- compute waves ----------------
   const int w = wave;
-  const int v0a = B0 * kSwRows + kSwRPW * w;
-  const int v0b = v0a + 1;
+  const int v0top = B0 * kSwRows + kSwRPW * w;
   const int v1 = B1 * kSwLanes + j;
-  const bool row_a = v0a <= sd.n0, row_b = v0b <= sd.n0;
   const bool col_ok = v1 <= sd.n1;
-  int r0a = (row_a && v0a >= 1) ? (int)sd.s0[v0a - 1] : 0;
-  int r0b = row_b ? (int)sd.s0[v0b - 1] : 0;
-  int r1 = (row_a && col_ok && v1 >= 1) ? (int)sd.s1[v1 - 1] : 0;
-  bad = bad || r0a >= alpha || r0b >= alpha || r1 >= alpha;
+  bool ok[kSwRPW];
+  int r0[kSwRPW];
+#pragma unroll
+  for (int u = 0; u < kSwRPW; ++u) {
+    const int v0 = v0top + u;
+    const bool row = v0 <= sd.n0;
+    ok[u] = row && col_ok;
+    int r = (row && v0 >= 1) ? (int)sd.s0[v0 - 1] : 0;
+    bad = bad || r >= alpha;
+    r0[u] = __builtin_amdgcn_readfirstlane(r >= alpha ? 0 : r);
+  }
+  int r1 = (v0top <= sd.n0 && col_ok && v1 >= 1) ? (int)sd.s1[v1 - 1] : 0;
+  bad = bad || r1 >= alpha;
   if (bad) atomicCAS(&ctrl->status, 0, -1);
-  r0a = __builtin_amdgcn_readfirstlane(r0a >= alpha ? 0 : r0a);
-  r0b = __builtin_amdgcn_readfirstlane(r0b >= alpha ? 0 : r0b);
   r1 = r1 >= alpha ? 0 : r1;
-  const bool x0 = w == kSwNW - 1 && B0 < sd.nb0 - 1 && row_b;
-  const bool x1 = B1 < sd.nb1 - 1 && row_a;
+  const bool x0 = w == kSwNW - 1 && B0 < sd.nb0 - 1 && v0top + kSwRPW - 1 <= sd.n0;
+  const bool x1 = B1 < sd.nb1 - 1 && v0top <= sd.n0;
   // the score: the corner cell's t = n2 is row uc of wave wc, lane jc, at
   // step sc of workgroup (n0 / kSwRows, n1 / 64)
   const int rc = sd.n0 % kSwRows;
@@ -630,11 +647,9 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
   const int uc = rc % kSwRPW;
   sw_barrier();  // the loader's halo of steps -1 and 0 is in LDS
   if (sd.egf)
-    sweep_rows<true>(sd, sm, B0, B1, w, j, row_a && col_ok, row_b && col_ok, r0a, r0b, r1, gap,
-                     tag, total, x0, x1, cw, sc, uc, jc);
+    sweep_rows<true>(sd, sm, B0, B1, w, j, ok, r0, r1, gap, tag, total, x0, x1, cw, sc, uc, jc);
   else
-    sweep_rows<false>(sd, sm, B0, B1, w, j, row_a && col_ok, row_b && col_ok, r0a, r0b, r1, gap,
-                      tag, total, x0, x1, cw, sc, uc, jc);
+    sweep_rows<false>(sd, sm, B0, B1, w, j, ok, r0, r1, gap, tag, total, x0, x1, cw, sc, uc, jc);
 }
 
 int launch_sweep3(const Plan &p, char *ws, const JobDev &jd, Ctrl *ctrl, int32_t flags,
