@@ -332,7 +332,7 @@ class _Marshalled:
                 "latency_ms_p99": round(float(np.percentile(lat, 99)), 3)}
 
 
-TRAFFIC_SOURCES = ("msa_sweep3.hip", "msa_plan.cpp", "msa_runtime.cpp")
+TRAFFIC_SOURCES = ("msa_sweep3.hip", "msa_internal.h", "msa_plan.cpp", "msa_runtime.cpp")
 
 
 def measured_traffic():
