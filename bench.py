@@ -534,8 +534,8 @@ def main():
                      "algorithmic_bytes": main_r["cells"],
                      "algorithmic_hbm_frac": round(main_r["cells"] / fill_s / 1e9 / PEAK_HBM_GBS,
                                                    4),
-                     "kernel": "sweep3_kernel (k=3 streaming fill: 8 rows x 64 lanes per "
-                               "workgroup, one workgroup per CU)",
+                     "kernel": "sweep3_kernel (k=3 streaming fill: 24 rows, three per compute "
+                               "wave, x 64 lanes per workgroup, one workgroup per CU)",
                      "ops_per_launch": 2 * main_r["neighbour_updates"]},
         "extra": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                       for kk, vv in v.items()} for k, v in extra.items()},

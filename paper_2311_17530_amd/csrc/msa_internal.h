@@ -189,7 +189,7 @@ constexpr int kCoMaxTotal = 32768;
 // sweeps the whole length; neighbouring workgroups exchange their boundary
 // lines through tagged values in two exchange regions of the workspace.
 constexpr int kSwNW = 8;           // compute waves per workgroup
-constexpr int kSwRPW = 2;          // rows per compute wave
+constexpr int kSwRPW = 3;          // rows per compute wave
 constexpr int kSwRows = kSwNW * kSwRPW;  // rows per workgroup
 constexpr int kSwLanes = 64;       // lanes (dimension-1 cells) per wave
 constexpr int kSwSeqMax = 16384;   // longest third sequence (kept in LDS)

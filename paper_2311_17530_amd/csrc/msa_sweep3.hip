@@ -6,23 +6,24 @@
 // instead of tile by tile:
 //
 //   - Lines.  A line is the run of cells (v0, v1, 0..n2) along dimension 2.
-//     A workgroup owns kSwRows x 64 lines: rows v0 = B0*kSwRows + 2w and
-//     2w + 1 (wave w's upper and lower row) and columns v1 = B1*64 + j (lane
-//     j), and sweeps them over the whole length in steps: at block step s,
-//     lane j of wave w computes cell t = s - j - w of both its lines, the
-//     upper one first.  Every neighbour v - b of that cell was computed by
-//     the same lane (in this step for the lower row's neighbours in the
-//     upper row), the lane to its left (v1 - 1) or the wave above (v0 - 1)
-//     one to three steps earlier, so a step needs no wait beyond one barrier.
-//     Two rows per wave halve the workgroups along dimension 0, and with
-//     them the hand-offs between workgroups on the sweep's critical path.
+//     A workgroup owns kSwRows x 64 lines: rows v0 = B0*kSwRows + kSwRPW*w
+//     + u, u = 0 .. kSwRPW - 1 (wave w's rows, top to bottom) and columns
+//     v1 = B1*64 + j (lane j), and sweeps them over the whole length in
+//     steps: at block step s, lane j of wave w computes cell t = s - j - w of
+//     each of its lines, top row first.  Every neighbour v - b of that cell
+//     was computed by the same lane (in this step for a row's neighbours in
+//     the row above it in the same wave), the lane to its left (v1 - 1) or
+//     the wave above (v0 - 1) one to three steps earlier, so a step needs no
+//     wait beyond one barrier.  Several rows per wave divide the workgroups
+//     along dimension 0, and with them the hand-offs between workgroups on
+//     the sweep's critical path, at the cost of longer steps.
 //   - Exchange inside a wave: lane j - 1's previous output arrives by a DPP
 //     wave shift (wave_shr:1); outputs of two steps back are kept in
-//     registers.  Between waves: each wave writes its lower row's outputs to
+//     registers.  Between waves: each wave writes its last row's outputs to
 //     an LDS ring of 4 steps, read by the wave below one or two steps later.
 //     Entry 0 of a ring row is the value of the row's lane -1 (the workgroup
 //     to the left), so every lane reads its neighbours at fixed offsets; the
-//     upper rows' lane -1 values have an array of their own (h0).
+//     other rows' lane -1 values have an array of their own (h0).
 //   - Exchange between workgroups: the outputs of the last row go to region
 //     X0 and those of lane 63 of every row to region X1, each value tagged
 //     with the launch's epoch in its low 3 bits (keys keep those bits clear);
@@ -57,7 +58,7 @@ namespace msa {
 namespace {
 
 constexpr int kSwRing = 4;        // LDS rings (outputs, halo rows): 4 steps
-constexpr int kSwPf = 8;          // loader prefetch distance (steps)
+constexpr int kSwPf = 2;          // loader prefetch distance (steps)
 constexpr int kSwUnroll = 16;     // steps per unrolled group (direction flush)
 constexpr int kSwRow = 65;        // ring row: the lane-(-1) entry + 64 lanes
 constexpr int kSwSeqPad = 128;    // LDS bytes around the third sequence
@@ -90,7 +91,7 @@ struct Sweep3Dev {
 };
 
 struct SwSmem {
-  int32_t ring[kSwRing][kSwNW][kSwRow];    // wave w's lower row at step s: slot s % 4
+  int32_t ring[kSwRing][kSwNW][kSwRow];    // wave w's last row at step s: slot s % 4
   int32_t in0[kSwRing][kSwRow];            // the row above the workgroup (wave -1)
   int32_t h0[kSwRing][kSwNW][kSwRPW - 1];  // lane -1 of wave w's rows above its last
   int32_t junk[64];                        // loader lanes without a halo value write here
@@ -118,10 +119,10 @@ __device__ __forceinline__ void sw_store(int32_t *p, int32_t v) {
 //   - the row above: in0[s % 4] entry i = cell (B0*kSwRows - 1, B1*64 - 1 + i,
 //     s + 2 - i) = X0[B0-1][B1*64 + s + 1][B1*64 - 1 + i] (element 0 of lane
 //     i; entry 64 is element 1 of lane 0);
-//   - lane -1 of row r = 2w + u (wave w's upper row u = 0, lower row u = 1):
-//     cell (B0*kSwRows + r, B1*64 - 1, s + 2 - w) = X1[B1-1][B0*kSwRows + r]
-//     [s + 2 - w] (element 1 of lane 1 + r), to h0[(s + 1) % 4][w] (u = 0) or
-//     ring[(s + 1) % 4][w][0] (u = 1);
+//   - lane -1 of row r = kSwRPW*w + u (wave w's row u): cell
+//     (B0*kSwRows + r, B1*64 - 1, s + 2 - w) = X1[B1-1][B0*kSwRows + r]
+//     [s + 2 - w] (element 1 of lane 1 + r), to h0[(s + 1) % 4][w][u] (u <
+//     kSwRPW - 1) or ring[(s + 1) % 4][w][0] (the wave's last row);
 // and issues the loads of step s + kSwPf.  A cell outside the tensor, or
 // without a workgroup before this one, reads -infinity.  Every lane issues
 // both loads every step (an address clamped into its element's window of
