@@ -119,7 +119,7 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
     q.sw_nb0 = (q.n[0] + 1 + kSwRows - 1) / kSwRows;
     q.sw_nb1 = (q.n[1] + 1 + kSwLanes - 1) / kSwLanes;
     q.x0_plane = ((int64_t)q.n[1] + q.n[2] + 1) * ((int64_t)q.n[1] + 1);
-    q.x1_plane = ((int64_t)q.n[0] + 1) * ((int64_t)q.n[2] + 1);
+    q.x1_plane = ((int64_t)q.n[0] + 1) * ((int64_t)q.n[2] + kSwNW);  // X1[e = v2 + w][v0]
     q.off_x0 = o;
     o = align256(o + std::max<int64_t>((q.sw_nb0 - 1) * q.x0_plane * 4, 256));
     q.off_x1 = o;
@@ -133,8 +133,11 @@ int make_plan(const int32_t *lens, int32_t k, Plan *p) {
 
 // The streaming k = 3 fill covers the plain and the end-gap-free modes.
 bool sweep3_eligible(const Plan &p, int alpha, int32_t flags) {
+  // the loader keeps each exchange element's offset within its window of
+  // n2 + 1 steps as 32 bits: n2 steps of n1 + 1 (X0) or n0 + 1 (X1) words
+  const int64_t wmax = (int64_t)p.n[2] * ((int64_t)std::max(p.n[0], p.n[1]) + 1);
   return p.k == 3 && (flags & ~kEndGapsFree) == 0 && alpha >= 1 && alpha <= kSwSubMax &&
-         p.n[2] <= kSwSeqMax;
+         p.n[2] <= kSwSeqMax && wmax < ((int64_t)1 << 31);
 }
 
 void make_tile_order(const Plan &p, std::vector<int32_t> *order) {

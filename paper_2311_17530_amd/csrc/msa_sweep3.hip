@@ -79,7 +79,7 @@ struct Sweep3Dev {
   const int8_t *sub;
   int32_t *x0;                // X0[b][d][v1], b < nb0 - 1, d = v1 + v2
   int64_t x0_plane;
-  int32_t *x1;                // X1[b][v0][v2], b < nb1 - 1
+  int32_t *x1;                // X1[b][e][v0], b < nb1 - 1, e = v2 + w (w: the row's wave)
   int64_t x1_plane;
   uint8_t *dir;               // tile-major direction blocks
   int32_t ts0, ts1;           // tile strides of dimensions 0 and 1 (dimension 2: 1)
@@ -120,9 +120,9 @@ __device__ __forceinline__ void sw_store(int32_t *p, int32_t v) {
 //     s + 2 - i) = X0[B0-1][B1*64 + s + 1][B1*64 - 1 + i] (element 0 of lane
 //     i; entry 64 is element 1 of lane 0);
 //   - lane -1 of row r = kSwRPW*w + u (wave w's row u): cell
-//     (B0*kSwRows + r, B1*64 - 1, s + 2 - w) = X1[B1-1][B0*kSwRows + r]
-//     [s + 2 - w] (element 1 of lane 1 + r), to h0[(s + 1) % 4][w][u] (u <
-//     kSwRPW - 1) or ring[(s + 1) % 4][w][0] (the wave's last row);
+//     (B0*kSwRows + r, B1*64 - 1, s + 2 - w) = X1[B1-1][s + 2][B0*kSwRows + r]
+//     (element 1 of lane 1 + r), to h0[(s + 1) % 4][w][u] (u < kSwRPW - 1) or
+//     ring[(s + 1) % 4][w][0] (the wave's last row);
 // and issues the loads of step s + kSwPf.  A cell outside the tensor, or
 // without a workgroup before this one, reads -infinity.  Every lane issues
 // both loads every step (an address clamped into its element's window of
@@ -188,9 +188,11 @@ struct SwLoader {
                                  ? &sm.h0[(k + 1) & (kSwRing - 1)][w][r % kSwRPW]
                                  : &sm.ring[(k + 1) & (kSwRing - 1)][w][0]) -
                             rbase);
+      // X1 is indexed by e = t + w, so one step's values of all rows are
+      // adjacent words (the left workgroup stores them in one step too)
       if (B1 > 0 && v0 <= sd.n0)
-        set(1, sd.x1 + (int64_t)(B1 - 1) * sd.x1_plane + (int64_t)v0 * (sd.n2 + 1),
-            w - 2, 1, sd.n2, s_first);
+        set(1, sd.x1 + (int64_t)(B1 - 1) * sd.x1_plane + (int64_t)w * (sd.n0 + 1) + v0, w - 2,
+            sd.n0 + 1, sd.n2, s_first);
     }
   }
 
@@ -306,11 +308,12 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
   const int32_t *const sub_r1 = sm.sub8 + r1 * kSwSubMax;
   const int jw = j + w;
   // exchange stores: cell (v0, v1, t) of the last row at X0[B0][v1 + t][v1]
-  // (v1 + t = B1*64 + s - w); lane 63's cells at X1[B1][v0][t] (t = s - 63 - w)
+  // (v1 + t = B1*64 + s - w); lane 63's cells at X1[B1][t + w][v0] = X1[B1][s - 63][v0]
   int32_t *const x0b = sd.x0 + (int64_t)B0 * sd.x0_plane +
                        (int64_t)(B1 * kSwLanes - w) * (sd.n1 + 1) + v1;
   const int64_t x0inc = sd.n1 + 1;
-  int32_t *const x1t = sd.x1 + (int64_t)B1 * sd.x1_plane + (int64_t)v0top * (sd.n2 + 1) - (63 + w);
+  int32_t *const x1t = sd.x1 + (int64_t)B1 * sd.x1_plane - (int64_t)63 * (sd.n0 + 1) + v0top;
+  const int64_t x1inc = sd.n0 + 1;
   const bool lane63 = j == 63;
   // end-gap-free: boundary cells (some v_i = 0), far lanes (v0 = n0 or
   // v1 = n1; every lane's cell t = n2 is far too), and the row-major index of
@@ -432,7 +435,7 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
         if (lane63) {
 #pragma unroll
           for (int u = 0; u < R; ++u)
-            if (ok[u] && in_t) sw_store(x1t + (int64_t)u * (sd.n2 + 1) + s, out[u] | tag);
+            if (ok[u] && in_t) sw_store(x1t + (int64_t)s * x1inc + u, out[u] | tag);
         }
       }
       // the score: the corner cell (n0, n1, n2) (wave-uniform test)
