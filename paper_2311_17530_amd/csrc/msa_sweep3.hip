@@ -412,7 +412,16 @@ __device__ __forceinline__ void sweep_row(const Sweep3Dev &sd, SwSmem &sm, int B
           if (u == 0) bst = (j == 0 && t == 0) ? 7 : bst;
         }
         best[u] = bst;
-        out[u] = (ok[u] && in_t) ? (bst & ~7) : kNegKey;
+        // Plain mode: a cell outside the tensor (t < 0, t > n2, v0 > n0,
+        // v1 > n1) may keep what its neighbours give it, since no cell inside
+        // reads it (a cell's neighbours have no larger coordinate), and cells
+        // t < 0 see only -infinity from the halo and stay far below any score.
+        // (Exchange stores and direction runs test validity themselves.)
+        // End-gap-free mode keeps -infinity there: that form measured faster.
+        if constexpr (kEgf)
+          out[u] = (ok[u] && in_t) ? (bst & ~7) : kNegKey;
+        else
+          out[u] = bst & ~7;
       }
       if constexpr (kEgf) {
         if (wfar || (unsigned)(s - w - n2) < 64u) {
