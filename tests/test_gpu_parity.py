@@ -193,14 +193,15 @@ def test_workspace_prepared_for_other_lengths_is_refused():
 
 
 def test_streaming_k3_block_edges():
-    # The k=3 fill streams lines of 8 rows x 64 lanes per workgroup: rows and
-    # lanes that end one before, on and one after a workgroup edge, several
-    # workgroups per dimension, long and empty third sequences, and a gap > 0
-    # (candidate keys that grow) -- every cell's decision compared.
+    # The k=3 fill streams lines of 24 rows (three per compute wave) x 64
+    # lanes per workgroup: rows and lanes that end one before, on and one
+    # after a workgroup or wave edge, several workgroups per dimension, long
+    # and empty third sequences, and a gap > 0 (candidate keys that grow) --
+    # every cell's decision compared.
     rng = np.random.Generator(np.random.PCG64(2600))
     for lens in ([7, 63, 20], [8, 64, 21], [9, 65, 5], [23, 130, 40], [40, 129, 90],
                  [1, 200, 15], [70, 1, 30], [15, 62, 300], [0, 64, 64], [16, 0, 9],
-                 [31, 127, 0]):
+                 [31, 127, 0], [22, 66, 13], [24, 63, 29], [47, 70, 11], [48, 65, 3]):
         protein = bool(sum(lens) % 2)
         sub, gap = protein_scoring() if protein else dna_scoring()
         seqs = [rng.integers(0, sub.shape[0], size=n).astype(np.uint8) for n in lens]
@@ -209,8 +210,8 @@ def test_streaming_k3_block_edges():
     sub = (np.triu(m) + np.triu(m, 1).T).astype(np.int8)
     seqs = [rng.integers(0, 4, size=n).astype(np.uint8) for n in (25, 70, 33)]
     check_device(seqs, sub, 2)
-    # cell (9, 64, 0) takes mask 3 from the left workgroup's halo entry of
-    # the row above at t = 0 (wave 1, lane 0, the ring slot before step 0)
+    # cell (9, 64, 0) takes mask 3 from the left workgroup's halo value of
+    # the row above at t = 0 (lane 0, the slot written before step 0)
     r5 = np.random.Generator(np.random.PCG64(5))
     sub, gap = protein_scoring()
     seqs = [r5.integers(0, 20, size=n).astype(np.uint8) for n in (10, 66, 1)]
