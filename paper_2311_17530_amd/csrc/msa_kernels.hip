@@ -1008,7 +1008,6 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb,
 
   int v[K], c[K], q[K];
   int Li = 0;                      // path length so far (sum n_i < 2^31)
-  int rem = (int)jd.total_len;     // steps still allowed
   int pbuf = 0;  // path bytes L & ~63 .. L - 1, one per lane, flushed every 64
   auto emit = [&](int b) {
     pbuf = tid == (Li & 63) ? b : pbuf;
@@ -1081,35 +1080,67 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb,
       }
     }
     __syncthreads();
-    bool leave = false;
-    while (!done && !leave) {
+    // The walk inside the tile tracks only the tile position q and its byte
+    // offset d; v = base + q follows when the walk leaves.  A cell with some
+    // v_i = 0 (the end of the walk) lies only in a tile with c_i = 0, where
+    // q_i = v_i; elsewhere the loop checks nothing but the mask and the exit.
+    // Every step lowers sum(v) by at least one, so the walk takes at most
+    // sum n_i steps (the path's capacity) before it ends or steps below some
+    // v_i = 0, which the exit check below catches.
+    int base[K];
+    uint32_t zmask = 0;  // dimensions with c_i = 0
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      base[i] = c[i] == 0 ? 0 : (c[i] - 1) * T + 1;
+      zmask |= (uint32_t)(c[i] == 0) << i;
+    }
+    bool bad = false;
+    for (;;) {
       // every lane walks the same path: keep the walk state wave-uniform
       const int byte = __builtin_amdgcn_readfirstlane(dirb[d]);
       const int b = coopt ? (byte ? __builtin_ctz(byte) + 1 : 0) : M - (byte & M);
-      int vor = 0, qor = 0;
-      bool anyz = false;
+      if (b == 0) {  // corrupt decision data: a cell without a move
+        bad = true;
+        break;
+      }
+      int qor = 0;
 #pragma unroll
       for (int i = 0; i < K; ++i) {
         const int bi = (b >> i) & 1;
-        v[i] -= bi;
         q[i] -= bi;
         d -= bi * C::dstride(i);
-        vor |= v[i];
         qor |= q[i];
-        anyz = anyz || v[i] == 0;
       }
-      // corrupt decision data (mask 0, a step below v_i = 0, a path longer
-      // than sum n_i): stop, never step outside the tensor
-      if (b == 0 || vor < 0 || rem <= 0) {
-        status = ST_EDEVICE;
-        done = true;
-        break;
-      }
-      --rem;
       emit(b);
-      done = egf ? anyz : vor == 0;
-      leave = qor < 0;
+      if (qor < 0) break;  // left the tile
+      if (zmask != 0) {
+        // the end of the walk: every v_i = 0 (plain), some v_i = 0 (end gaps free)
+        bool stop = !egf;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          const bool z = ((zmask >> i) & 1) != 0 && q[i] == 0;
+          stop = egf ? (stop || z) : (stop && z);
+        }
+        if (stop) {
+          done = true;
+          break;
+        }
+      }
     }
+    // the step that left the tile may also have ended the walk
+    bool allz = true, anyz = false;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      v[i] = base[i] + q[i];
+      bad = bad || v[i] < 0;  // a step below v_i = 0: corrupt decision data
+      allz = allz && v[i] == 0;
+      anyz = anyz || v[i] == 0;
+    }
+    if (bad) {
+      status = ST_EDEVICE;
+      done = true;
+    }
+    done = done || (egf ? anyz : allz);
     if (done) break;
     // enter the next tile: its block was prefetched unless the walk left
     // through an edge or corner that is not in the prefetched set
