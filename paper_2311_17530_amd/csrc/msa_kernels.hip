@@ -1095,9 +1095,23 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb,
       zmask |= (uint32_t)(c[i] == 0) << i;
     }
     bool bad = false;
+    // k <= 6: lane l reads the byte of the cell mask l below the current one,
+    // so the next step's byte is a register read (readlane by the decoded
+    // mask), and the read for the step after it is issued before this step's
+    // remaining work instead of after it.  A candidate outside the block
+    // reads a clamped address and is never used: a step to it leaves the tile.
+    // (k > 6: one uniform read per step.)
+    constexpr bool CAND = M < 64;
+    int loff = 0;
+    if constexpr (CAND) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) loff += ((tid & M) >> i & 1) * C::dstride(i);
+    }
+    int cand = CAND ? dirb[max(d - loff, 0)] : 0;
+    int byte = CAND ? __builtin_amdgcn_readlane(cand, 0) : 0;
     for (;;) {
       // every lane walks the same path: keep the walk state wave-uniform
-      const int byte = __builtin_amdgcn_readfirstlane(dirb[d]);
+      if constexpr (!CAND) byte = __builtin_amdgcn_readfirstlane(dirb[d]);
       const int b = coopt ? (byte ? __builtin_ctz(byte) + 1 : 0) : M - (byte & M);
       if (b == 0) {  // corrupt decision data: a cell without a move
         bad = true;
@@ -1110,6 +1124,10 @@ __device__ void traceback_job(const JobDev &jd, int status_in, uint8_t *dirb,
         q[i] -= bi;
         d -= bi * C::dstride(i);
         qor |= q[i];
+      }
+      if constexpr (CAND) {
+        byte = __builtin_amdgcn_readlane(cand, b);  // the next cell's byte
+        cand = dirb[max(d - loff, 0)];              // its successors' bytes
       }
       emit(b);
       if (qor < 0) break;  // left the tile
