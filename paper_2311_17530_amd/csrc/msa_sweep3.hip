@@ -577,7 +577,15 @@ __global__ __launch_bounds__(kSwThreads) void sweep3_kernel(Sweep3Dev sd, Ctrl *
     }
     T -= cnt;
   }
-  const int nsteps = sd.n2 + 1 + 63 + (kSwNW - 1);
+  // Steps until the block's last cell inside the tensor: lane j of wave w
+  // computes t = n2 at step n2 + j + w.  A ragged block (the last along
+  // dimension 0 or 1) stops after its last valid lane and wave instead of
+  // sweeping the skew of lanes and waves that hold no cell; such a block has
+  // no workgroup after it along that dimension, so no one waits for the
+  // exchange values it skips.  (Every wave and the loader take the same count.)
+  const int jmax = min(kSwLanes - 1, sd.n1 - B1 * kSwLanes);
+  const int wmax = min(kSwNW - 1, (sd.n0 - B0 * kSwRows) / kSwRPW);
+  const int nsteps = sd.n2 + 1 + jmax + wmax;
   const int total = (nsteps + kSwUnroll - 1) / kSwUnroll * kSwUnroll;
 
   if (wave == kSwNW) {
